@@ -1,0 +1,356 @@
+"""Pins of the FP64 CPU oracle against what the paper and the mathematics fix.
+
+Each test names the passage of the paper it checks and what independent
+fact it uses (a closed form, an identity, a textbook scheme property,
+brute force on tiny grids).  None of them compares the oracle with itself.
+"""
+import numpy as np
+import pytest
+
+import oracle as orc
+import workloads as wl
+from oracle import dense
+from physics_refs import (boltzmann_average_1d, chi_brownian, linear_response_1d,
+                          lyapunov_moments)
+
+
+def harmonic_ll(N=48, K=2, **kw):
+    """One harmonic mode, linear-linear coupling only (V_SL = 0)."""
+    return wl.workload("one_mode_48", Nq=[N], Np=[N], K=K, g3=[0.0], g4=[0.0], VSL=[0.0], **kw)
+
+
+# ---------------------------------------------------------------------------
+# hierarchy index set (Sec. II B): the set {n : |n| <= K} and its order
+# ---------------------------------------------------------------------------
+
+def test_element_set_and_order():
+    w = wl.workload("three_mode_24", Nq=[5] * 3, Np=[5] * 3)
+    got = [tuple(r) for r in orc.elements(w)]
+    assert got == [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (2, 0, 0), (1, 1, 0),
+                   (1, 0, 1), (0, 2, 0), (0, 1, 1), (0, 0, 2)]
+    for M, K, count in [(1, 3, 4), (2, 3, 10), (3, 2, 10), (3, 4, 35)]:
+        w = wl.workload("three_mode_24", M=M, K=K, Nq=[5] * M, Np=[5] * M)
+        assert orc.elements(w).shape == (count, M)
+
+
+# ---------------------------------------------------------------------------
+# compact sixth-order derivative (Sec. III B)
+# ---------------------------------------------------------------------------
+
+def test_compact_derivative_matches_lele_modified_wavenumber():
+    """Far from the box ends the truncated scheme acts like the periodic one,
+    whose response to sin(k x) is k' cos(k x) with Lele's modified wavenumber
+    k' h = (14/9 sin kh + 1/18 sin 2kh) / (1 + 2/3 cos kh).  Each k weighs
+    alpha, the 7/9 and the 1/36 weights differently."""
+    N, h = 240, 0.05
+    x = np.arange(N) * h
+    for kh in (0.3, 0.9, 1.7, 2.6):
+        k = kh / h
+        y = orc.deriv_line(np.sin(k * x), h)
+        kmod = (14.0 / 9.0 * np.sin(kh) + 1.0 / 18.0 * np.sin(2 * kh)) / (1.0 + 2.0 / 3.0 * np.cos(kh)) / h
+        mid = slice(90, 150)
+        np.testing.assert_allclose(y[mid], kmod * np.cos(k * x[mid]), rtol=0, atol=1e-11 * k)
+
+
+def test_compact_derivative_sixth_order_convergence():
+    """Error on a Gaussian well inside the box falls by ~2^6 per halving of h."""
+    errs = []
+    for N in (24, 48, 96):
+        L = 6.0
+        h = 2 * L / N
+        x = -L + (np.arange(N) + 0.5) * h
+        y = orc.deriv_line(np.exp(-x ** 2), h)
+        errs.append(np.abs(y + 2 * x * np.exp(-x ** 2)).max())
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > 5.5), rates
+
+
+def test_compact_derivative_zero_ghost_closure():
+    """Rows 0 and N-1 are the truncated Toeplitz rows printed in Sec. III B:
+    the line solve equals the dense solve of A y = B f / h."""
+    rng = np.random.default_rng(0)
+    for N in (5, 7, 12, 33):
+        f = rng.standard_normal(N)
+        A, B = dense.compact_matrices(N)
+        np.testing.assert_allclose(orc.deriv_line(f, 0.3), np.linalg.solve(A, B @ f) / 0.3,
+                                   rtol=1e-13, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# right-hand side of Eq. (eq:HEOM): two independent assemblies agree
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", ["m1", "m2", "m3"])
+def test_rhs_matches_kronecker_assembly(case):
+    if case == "m1":
+        w = wl.workload("one_mode_48", Nq=[8], Np=[9], K=3)
+    elif case == "m2":
+        w = wl.workload("two_mode_32", Nq=[6, 5], Np=[5, 6], K=2)
+        w["g21"][0][1], w["g12"][0][1] = 0.07, -0.04
+        w["zeta"], w["gamma"], w["VSL"] = [0.3, 0.5], [1.0, 1.7], [0.3, -0.2]
+    else:
+        w = wl.workload("three_mode_24", Nq=[5, 6, 5], Np=[5, 5, 6], K=1)
+    W = wl.noise_state(w, seed=3)
+    G = dense.generator(w)
+    ref = (G @ W.ravel()).reshape(W.shape)
+    got = orc.rhs(w, W)
+    assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_rhs_point_matches_full_rhs():
+    w = wl.workload("two_mode_32", Nq=[7, 6], Np=[6, 8], K=2)
+    W = wl.noise_state(w, seed=5)
+    full = orc.rhs(w, W).reshape(W.shape[0], -1)
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        e = int(rng.integers(W.shape[0]))
+        i = int(rng.integers(full.shape[1]))
+        assert abs(orc.rhs_point(w, W, e, i) - full[e, i]) <= 1e-13 * np.abs(full).max()
+
+
+# ---------------------------------------------------------------------------
+# classical RK4: one step is the degree-4 Taylor polynomial of exp(dt L)
+# ---------------------------------------------------------------------------
+
+def test_rk4_is_fourth_order_taylor_of_generator():
+    w = wl.workload("one_mode_48", Nq=[8], Np=[8], K=2)
+    G = dense.generator(w).toarray()
+    dt = 0.01
+    X = dt * G
+    T4 = np.eye(G.shape[0]) + X + X @ X / 2 + X @ X @ X / 6 + X @ X @ X @ X / 24
+    W = wl.noise_state(w, seed=7)
+    ref = W.ravel()
+    for _ in range(3):
+        ref = T4 @ ref
+    got = orc.rk4(w, W, 3, dt).ravel()
+    assert np.linalg.norm(got - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+# ---------------------------------------------------------------------------
+# Boltzmann stationarity and conservation (Sec. II B)
+# ---------------------------------------------------------------------------
+
+def test_boltzmann_is_stationary_to_sixth_order():
+    """exp(-beta H) with W_{n>0} = 0 is an exact stationary state of the
+    continuous hierarchy (L e^{-beta H} = 0 and Theta e^{-beta H} = 0), so the
+    discrete residual must vanish at the scheme's order."""
+    res = []
+    for N in (24, 48, 96):
+        w = wl.workload("one_mode_48", Nq=[N], Np=[N], K=2)
+        W = orc.boltzmann(w)
+        res.append(np.linalg.norm(orc.rhs(w, W)) / np.linalg.norm(W))
+    rates = np.log2(np.array(res[:-1]) / np.array(res[1:]))
+    assert np.all(rates > 5.5), (res, rates)
+    # two coupled anharmonic modes with SL coupling
+    w = wl.workload("two_mode_32", Nq=[24, 24], Np=[24, 24], K=2)
+    W = orc.boltzmann(w)
+    assert np.linalg.norm(orc.rhs(w, W)) / np.linalg.norm(W) < 2e-2
+
+
+def test_boltzmann_normalisation_and_moments_match_quadrature():
+    """Z and <q>, <q^2> of the discrete Boltzmann state against adaptive
+    quadrature of exp(-beta U) (one anharmonic mode)."""
+    w = wl.workload("one_mode_48")
+    W = orc.boltzmann(w)
+    mom = orc.moments(w, W, 0, 0)
+    U = lambda q: 0.5 * q ** 2 - 0.15 * q ** 3 / 6 + 0.02 * q ** 4 / 24
+    assert abs(mom[0] - 1.0) < 1e-13
+    assert abs(mom[1] - boltzmann_average_1d(U, lambda q: q, 2.0, 6.0)) < 1e-9
+    assert abs(mom[3] - boltzmann_average_1d(U, lambda q: q * q, 2.0, 6.0)) < 1e-9
+    assert abs(mom[4] - 0.5) < 1e-9  # <p^2> = m / beta
+
+
+def test_weighted_integral_of_w0_is_conserved_exactly_for_interior_states():
+    """Every n = 0 term of Eq. (eq:HEOM) is a derivative along its own axis
+    with a coefficient constant on that line.  Under the weights (0.8 at both
+    ends) the weighted sum of a compact derivative reduces to the two outer
+    values at each end of the line, so a state that is zero in the two outer
+    layers of every axis has a right-hand side with zero weighted integral."""
+    w = wl.workload("two_mode_32", Nq=[9, 10], Np=[11, 9], K=2)
+    W = wl.noise_state(w, seed=11)
+    for ax in range(1, W.ndim):
+        idx = [slice(None)] * W.ndim
+        for i in (0, 1, -2, -1):
+            idx[ax] = i
+            W[tuple(idx)] = 0.0
+    r = orc.rhs(w, W)
+    total = orc.moments(w, r, 0, 0)[0]
+    scale = orc.moments(w, np.abs(r), 0, 0)[0]
+    assert abs(total) < 1e-14 * scale
+    # a plain (unweighted) sum does not have this property
+    assert abs(r[0].sum()) > 1e-6 * np.abs(r[0]).sum()
+
+
+def test_weighted_integral_of_w0_is_conserved_in_time():
+    """Time-integrated version on a resolved grid: Boltzmann start with a
+    non-stationary first element; the integral of W_0 keeps its value."""
+    w = wl.workload("one_mode_48", K=3)
+    W = orc.boltzmann(w)
+    W[1] = 0.3 * W[0]
+    q0 = orc.moments(w, W, 0, 0)[0]
+    q1 = orc.moments(w, orc.rk4(w, W, 200, 0.005), 0, 0)[0]
+    assert abs(q1 - q0) < 1e-12
+
+
+def test_liouvillian_conserves_energy():
+    """d/dt int H W = int H {H, W} = 0 for zeta = 0: pins dU/dq_s against U,
+    including the pair couplings g_ss', g_{s^2 s'}, g_{s s'^2}."""
+    w = wl.workload("two_mode_32", Nq=[28, 28], Np=[28, 28], K=0, zeta=[0.0, 0.0])
+    w["g21"][0][1], w["g12"][0][1] = 0.08, -0.05
+    W = orc.boltzmann(w)
+    # a non-stationary start: the Boltzmann state of a shifted potential
+    W2 = np.roll(W, 2, axis=1)
+    r = orc.rhs(w, W2)
+    drift = abs(orc.energy(w, r))
+    scale = orc.energy(w, np.abs(r))
+    assert drift < 1e-6 * scale, (drift, scale)
+
+
+# ---------------------------------------------------------------------------
+# closed forms of the linear model: harmonic U, V = V_LL q
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("K", [1, 3])
+def test_harmonic_ll_linear_response_closed_form(K):
+    """R^(1)(t) = -mu^2 chi(t) with chi from the generalized Langevin equation;
+    the hierarchy is exact at any K >= 1 for this model (Eqs. (1Dresponse),
+    (eq:HEOM))."""
+    w = harmonic_ll(N=48, K=K)
+    A = wl.optical(1, lin=[1.3])
+    R = orc.response_1d(w, A, orc.boltzmann(w), 801, 1, 0.005)
+    t = np.arange(801) * 0.005
+    ref = -1.3 ** 2 * chi_brownian(t, 1.0, 1.0, 0.3, 1.0, 1.0)
+    assert np.abs(R - ref).max() < 1e-9 * np.abs(ref).max()
+
+
+def test_free_oscillator_response():
+    """zeta = 0 and K = 0: R^(1)(t) = -mu^2 sin(omega t) / (m omega)."""
+    w = wl.workload("one_mode_48", Nq=[48], Np=[48], K=0, g3=[0.0], g4=[0.0], zeta=[0.0],
+                    omega=[1.4], Lq=[6.0 / 1.4])
+    A = wl.optical(1, lin=[0.8])
+    R = orc.response_1d(w, A, orc.boltzmann(w), 601, 1, 0.005)
+    t = np.arange(601) * 0.005
+    ref = -0.8 ** 2 * np.sin(1.4 * t) / 1.4
+    assert np.abs(R - ref).max() < 1e-9
+
+
+def test_two_mode_bilinear_linear_response_closed_form():
+    """Two harmonic modes coupled by g_12 q_1 q_2, each with its own Drude bath:
+    R^(1) against the matrix exponential of the mean dynamics.  The p grid
+    converges slowly (Sec. III A), so the check is the error level at N = 20
+    and its fall from N = 16; doubling g_12 moves the closed form by 14%."""
+    errs = []
+    for N in (16, 20):
+        w = wl.workload("two_mode_32", Nq=[N, N], Np=[N, N], K=1, g3=[0.0, 0.0], g4=[0.0, 0.0],
+                        VSL=[0.0, 0.0])
+        w["g2"][0][1] = 0.3
+        A = wl.optical(2, lin=[1.0, 0.6])
+        R = orc.response_1d(w, A, orc.boltzmann(w), 21, 10, 0.005)
+        ref = linear_response_1d(w, [1.0, 0.6], np.arange(21) * 10 * 0.005)
+        errs.append(np.abs(R - ref).max() / np.abs(ref).max())
+    assert errs[1] < 1e-2 and errs[0] / errs[1] > 3.0, errs
+
+
+@pytest.mark.parametrize("K", [2, 3])
+def test_second_moments_pin_the_n_factor(K):
+    """Second moments of W_0 from a hot, displaced Gaussian start follow the
+    Lyapunov equation of the (q, p, f) stochastic process.  The moment system
+    involves W_2, so a Theta coupling without the factor n_s (Eq. (eq:HEOM)
+    as printed) misses by ~1e-2; with it the error is ~1e-6."""
+    w = harmonic_ll(N=48, K=K)
+    N, L = 48, 6.0
+    x = -L + (np.arange(N) + 0.5) * (2 * L / N)
+    q0, p0, s2 = 0.7, -0.4, 1.0
+    g = lambda c: np.exp(-(x - c) ** 2 / (2 * s2)) / np.sqrt(2 * np.pi * s2)
+    W = np.zeros(orc.state_shape(w))
+    W[0] = np.outer(g(q0), g(p0))
+    steps, dt = 400, 0.005
+    mom = orc.moments(w, orc.rk4(w, W, steps, dt), 0, 0)
+    mean, cov = lyapunov_moments(1.0, 1.0, 0.3, 1.0, 1.0, 2.0, [q0, p0, 0.0],
+                                 np.diag([s2, s2, 0.3 / 2.0]), steps * dt)
+    ref = [1.0, mean[0], mean[1], cov[0, 0] + mean[0] ** 2, cov[1, 1] + mean[1] ** 2,
+           cov[0, 1] + mean[0] * mean[1]]
+    np.testing.assert_allclose(mom, ref, rtol=0, atol=1e-5)
+
+
+# ---------------------------------------------------------------------------
+# excitation and observable: sum rules (Eqs. (Opticalexc), (1Dresponse), (2Dresponse))
+# ---------------------------------------------------------------------------
+
+def test_linear_response_sum_rules():
+    """R^(1)(0) = 0 and dR^(1)/dt(0) = -<(dA/dq)^2>_Boltzmann / m (W_{n>0} = 0)."""
+    w = wl.workload("one_mode_48", K=2)
+    Wb = orc.boltzmann(w)
+    A = w["A"]  # q + 0.1 q^2
+    u = orc.perturb(w, A, Wb)
+    assert abs(orc.observe(w, A, u)) < 1e-13
+    rdot = orc.observe(w, A, orc.rhs(w, u))
+    U = lambda q: 0.5 * q ** 2 - 0.15 * q ** 3 / 6 + 0.02 * q ** 4 / 24
+    ref = -boltzmann_average_1d(U, lambda q: (1 + 0.2 * q) ** 2, 2.0, 6.0)
+    assert abs(rdot - ref) < 1e-6 * abs(ref)
+
+
+def test_excitation_first_moment_in_p():
+    """int p_s (X^x W) dq dp = -int dX/dq_s W dq dp (integration by parts in p)."""
+    w = wl.workload("two_mode_32", Nq=[24, 24], Np=[24, 24], K=1)
+    W = orc.boltzmann(w)
+    X = wl.optical(2, lin=[0.7, -1.1], quad=[[0.2, 0.05], [0.05, -0.3]])
+    u = orc.perturb(w, X, W)
+    for s in range(2):
+        lhs = orc.moments(w, u, 0, s)[2]
+        # -int (lin_s + sum_t quad_st q_t) W
+        rhs = -(X["lin"][s] * orc.moments(w, W, 0, s)[0]
+                + sum(X["quad"][s][t] * orc.moments(w, W, 0, t)[1] for t in range(2)))
+        assert abs(lhs - rhs) < 1e-8
+
+
+def test_second_order_response_vanishes_at_t2_zero():
+    """R^(2)(t2 = 0, t1) = sum_s int C dB/dq_s dU_0/dp_s = 0 (integration by
+    parts in p); discretely it is left with the values at the p-box edges,
+    which are negligible on a resolved grid."""
+    w = wl.workload("one_mode_48", K=2)
+    B = wl.optical(1, lin=[1.0], quad=[[0.1]])
+    R = orc.response_2d(w, w["A"], B, w["A"], orc.boltzmann(w), 6, 3, 40, 40, 0.005)
+    assert np.abs(R[1:]).max() > 1e-3
+    assert np.abs(R[0]).max() < 1e-11 * np.abs(R[1:]).max()
+
+
+def test_second_order_response_parity_zero():
+    """Even U, odd V (V_SL = 0) and linear A, B, C on a symmetric grid: the
+    dynamics commute with (q, p, f) -> -(q, p, f), A^x W_eq is odd, B^x maps
+    odd to even, so R^(2) vanishes identically; quadratic B breaks it."""
+    w = wl.workload("two_mode_32", Nq=[10, 10], Np=[10, 10], K=2, g3=[0.0, 0.0], VSL=[0.0, 0.0])
+    Wb = orc.boltzmann(w)
+    lin = wl.optical(2, lin=[1.0, 0.7])
+    R0 = orc.response_2d(w, lin, lin, lin, Wb, 3, 4, 3, 3, 0.005)
+    quadB = wl.optical(2, lin=[1.0, 0.7], quad=[[0.0, 0.3], [0.3, 0.0]])
+    R1 = orc.response_2d(w, lin, quadB, lin, Wb, 3, 4, 3, 3, 0.005)
+    assert np.abs(R1).max() > 1e-6
+    assert np.abs(R0).max() < 1e-12 * np.abs(R1).max()
+
+
+# ---------------------------------------------------------------------------
+# spectra, Eqs. (1DIR_Raman), (2DThz_Raman): Fourier sums of known signals
+# ---------------------------------------------------------------------------
+
+def test_spectrum_1d_geometric_sum():
+    n, tau, lam, Om = 256, 0.05, 0.3, 2.0
+    t = np.arange(n) * tau
+    R = np.exp(-lam * t) * np.sin(Om * t)
+    omega, I = orc.spectrum_1d(R, tau)
+    z = lambda wv: np.exp((1j * wv - lam) * tau)
+    # sum_j e^{i w t_j} e^{-lam t_j} sin(Om t_j) = (S(w+Om) - S(w-Om)) / 2i
+    S = lambda wv: (1 - z(wv) ** n) / (1 - z(wv))
+    ref = omega * np.imag(tau * (S(omega + Om) - S(omega - Om)) / 2j)
+    np.testing.assert_allclose(I, ref, rtol=0, atol=1e-10 * np.abs(ref).max())
+    # and against numpy's inverse FFT (e^{+i} convention)
+    ref2 = omega * np.imag(tau * n * np.fft.ifft(R))
+    np.testing.assert_allclose(I, ref2, rtol=0, atol=1e-10 * np.abs(ref2).max())
+
+
+def test_spectrum_2d_against_fft():
+    rng = np.random.default_rng(2)
+    R = rng.standard_normal((16, 8))
+    _, _, I = orc.spectrum_2d(R, 0.1, 0.2)
+    ref = np.imag(0.1 * 0.2 * np.fft.fft2(R))
+    np.testing.assert_allclose(I, ref, rtol=0, atol=1e-12)
