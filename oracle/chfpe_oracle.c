@@ -15,11 +15,19 @@
  *     (eq:Phi), (eq:Theta); the Theta coupling into element n carries the
  *     factor n_s (the appendix form, Eq. (HEOM2FP-H), and the Fokker-Planck
  *     derivation of the Drude bath both have it)                (Sec. II B)
+ *   - the factorization of Sec. III A: every element is written as
+ *     W_n = exp(-beta H_sys / 2) h_n (the paper's e^{-beta U/2} psi_0(p)
+ *     prefactor); the smooth factor h_n is what is discretized.  In h the
+ *     hierarchy reads (L is unchanged because L exp(-beta H/2) = 0)
+ *       dh_n/dt = L h_n - sum_s n_s gamma_s h_n
+ *               + sum_s V_s' (d/dp_s - beta p_s / 2 m_s) h_{n+e_s}
+ *               + sum_s n_s (m_s zeta_s gamma_s / beta) V_s' (d/dp_s + beta p_s / 2 m_s) h_{n-e_s}
  *   - the compact sixth-order first derivative A f' = B f / h with
  *     alpha = 1/3 and right-hand-side weights 7/9 on f_{i+1}-f_{i-1} and
- *     1/36 on f_{i+2}-f_{i-2}; values outside the box are zero  (Sec. III B)
- *     The tridiagonal systems are solved by the Thomas algorithm (the paper
- *     uses parallel cyclic reduction, Sec. III C; both solve the same system).
+ *     1/36 on f_{i+2}-f_{i-2}, applied to h; values outside the box are
+ *     zero (Sec. III B).  The tridiagonal systems are solved by the Thomas
+ *     algorithm (the paper uses parallel cyclic reduction, Sec. III C; both
+ *     solve the same system).
  *   - the optical excitation X^x W = sum_s dX/dq_s dW/dp_s, Eq. (Opticalexc)
  *   - response functions, Eqs. (1Dresponse) and (2Dresponse), with the
  *     equilibrium obtained by propagation (Sec. IV B) and the t1/t2 double
@@ -31,6 +39,8 @@
  * lexicographic order.
  *
  * Layout of a state: W[e][q_1..q_M][p_1..p_M], C order, p_M fastest.
+ * States passed in and out are W; the right-hand side and the excitation
+ * convert to h internally and back.
  */
 #include <math.h>
 #include <stdint.h>
@@ -164,6 +174,13 @@ double orc_force(const orc_params *P, const double *q, int s) {
 /* dV_s/dq_s for V_s = V_LL q + V_SL q^2 / 2 */
 static double dV(const orc_params *P, int s, double x) { return P->VLL[s] + P->VSL[s] * x; }
 
+/* exp(-beta H_sys(q, p) / 2): W_n = factor * h_n */
+static double sym_factor(const orc_params *P, const double *q, const double *p) {
+  double H = orc_potential(P, q);
+  for (int s = 0; s < P->M; ++s) H += p[s] * p[s] / (2.0 * P->m[s]);
+  return exp(-0.5 * P->beta * H);
+}
+
 /* dX/dq_s for X(q) = sum lin_s q_s + 1/2 sum_{s,s'} quad_ss' q_s q_s' */
 double orc_optical_grad(const orc_params *P, const orc_optical *X, const double *q, int s) {
   double g = X->lin[s];
@@ -269,6 +286,28 @@ static void point_coords(const orc_params *P, const geom *g, int64_t idx, double
 /* right-hand side of Eq. (eq:HEOM)                                     */
 /* ------------------------------------------------------------------ */
 
+/* h = W / exp(-beta H/2) for every element */
+static void to_h(const orc_params *P, const geom *g, int ne, const double *W, double *h) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < g->E; ++i) {
+    double q[3], p[3];
+    point_coords(P, g, i, q, p);
+    const double f = sym_factor(P, q, p);
+    for (int e = 0; e < ne; ++e) h[(int64_t)e * g->E + i] = W[(int64_t)e * g->E + i] / f;
+  }
+}
+
+/* out = exp(-beta H/2) * out for every element */
+static void from_h(const orc_params *P, const geom *g, int ne, double *out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < g->E; ++i) {
+    double q[3], p[3];
+    point_coords(P, g, i, q, p);
+    const double f = sym_factor(P, q, p);
+    for (int e = 0; e < ne; ++e) out[(int64_t)e * g->E + i] *= f;
+  }
+}
+
 void orc_rhs(const orc_params *P, const double *W, double *out) {
   geom g;
   make_geom(P, &g);
@@ -277,23 +316,25 @@ void orc_rhs(const orc_params *P, const double *W, double *out) {
   int ne = orc_elements(P, nvec);
   const int64_t E = g.E;
   double *tmp = (double *)malloc(sizeof(double) * E);
+  double *h = (double *)malloc(sizeof(double) * E * ne);
+  to_h(P, &g, ne, W, h);
 
   for (int e = 0; e < ne; ++e) {
     const int *n = nvec + e * M;
-    const double *We = W + (int64_t)e * E;
+    const double *he = h + (int64_t)e * E;
     double *oe = out + (int64_t)e * E;
     memset(oe, 0, sizeof(double) * E);
 
-    /* L W_n = {H_sys, W_n} = sum_s dU/dq_s dW/dp_s - (p_s/m_s) dW/dq_s */
+    /* L h_n = {H_sys, h_n} = sum_s dU/dq_s dh/dp_s - (p_s/m_s) dh/dq_s */
     for (int s = 0; s < M; ++s) {
-      deriv_axis(g.dims, g.nd, M + s, g.hp[s], We, tmp);
+      deriv_axis(g.dims, g.nd, M + s, g.hp[s], he, tmp);
 #pragma omp parallel for schedule(static)
       for (int64_t i = 0; i < E; ++i) {
         double q[3], p[3];
         point_coords(P, &g, i, q, p);
         oe[i] += orc_force(P, q, s) * tmp[i];
       }
-      deriv_axis(g.dims, g.nd, s, g.hq[s], We, tmp);
+      deriv_axis(g.dims, g.nd, s, g.hq[s], he, tmp);
 #pragma omp parallel for schedule(static)
       for (int64_t i = 0; i < E; ++i) {
         double q[3], p[3];
@@ -302,51 +343,54 @@ void orc_rhs(const orc_params *P, const double *W, double *out) {
       }
     }
 
-    /* - sum_s n_s gamma_s W_n */
+    /* - sum_s n_s gamma_s h_n */
     double damp = 0.0;
     for (int s = 0; s < M; ++s) damp += n[s] * P->gamma[s];
     if (damp != 0.0) {
 #pragma omp parallel for schedule(static)
-      for (int64_t i = 0; i < E; ++i) oe[i] -= damp * We[i];
+      for (int64_t i = 0; i < E; ++i) oe[i] -= damp * he[i];
     }
 
-    /* + sum_s Phi_s W_{n+e_s},  Phi_s = V_s'(q_s) d/dp_s */
+    /* + sum_s Phi_s h_{n+e_s},  Phi_s -> V_s'(q_s) (d/dp_s - beta p_s / 2 m_s) */
     for (int s = 0; s < M; ++s) {
       int up[3] = {0, 0, 0};
       for (int t = 0; t < M; ++t) up[t] = n[t] + (t == s);
       int eu = find_element(nvec, ne, M, up);
       if (eu < 0) continue; /* outside the truncated set: W = 0 */
-      deriv_axis(g.dims, g.nd, M + s, g.hp[s], W + (int64_t)eu * E, tmp);
+      const double *hu = h + (int64_t)eu * E;
+      deriv_axis(g.dims, g.nd, M + s, g.hp[s], hu, tmp);
+      const double bm = P->beta / (2.0 * P->m[s]);
 #pragma omp parallel for schedule(static)
       for (int64_t i = 0; i < E; ++i) {
         double q[3], p[3];
         point_coords(P, &g, i, q, p);
-        oe[i] += dV(P, s, q[s]) * tmp[i];
+        oe[i] += dV(P, s, q[s]) * (tmp[i] - bm * p[s] * hu[i]);
       }
     }
 
-    /* + sum_s n_s Theta_s W_{n-e_s},
-     *   Theta_s = (m_s zeta_s gamma_s / beta) V_s' d/dp_s + zeta_s gamma_s p_s V_s' */
+    /* + sum_s n_s Theta_s h_{n-e_s},
+     *   Theta_s -> (m_s zeta_s gamma_s / beta) V_s' (d/dp_s + beta p_s / 2 m_s) */
     for (int s = 0; s < M; ++s) {
       if (n[s] == 0) continue;
       int dn[3] = {0, 0, 0};
       for (int t = 0; t < M; ++t) dn[t] = n[t] - (t == s);
       int ed = find_element(nvec, ne, M, dn);
-      const double *Wd = W + (int64_t)ed * E;
-      deriv_axis(g.dims, g.nd, M + s, g.hp[s], Wd, tmp);
+      const double *hd = h + (int64_t)ed * E;
+      deriv_axis(g.dims, g.nd, M + s, g.hp[s], hd, tmp);
       const double c1 = P->m[s] * P->zeta[s] * P->gamma[s] / P->beta;
-      const double c2 = P->zeta[s] * P->gamma[s];
+      const double bm = P->beta / (2.0 * P->m[s]);
       const double ns = (double)n[s];
 #pragma omp parallel for schedule(static)
       for (int64_t i = 0; i < E; ++i) {
         double q[3], p[3];
         point_coords(P, &g, i, q, p);
-        double v = dV(P, s, q[s]);
-        oe[i] += ns * (c1 * v * tmp[i] + c2 * p[s] * v * Wd[i]);
+        oe[i] += ns * c1 * dV(P, s, q[s]) * (tmp[i] + bm * p[s] * hd[i]);
       }
     }
   }
+  from_h(P, &g, ne, out);
   free(tmp);
+  free(h);
 }
 
 /* The right-hand side at one point (element e, point index idx), computed
@@ -365,18 +409,23 @@ double orc_rhs_point(const orc_params *P, const double *W, int e, int64_t idx) {
   point_coords(P, &g, idx, q, p);
 
   double f[64], y[64];
-  /* derivative along axis ax of element ee, evaluated at this point */
-#define LINE_DERIV(ee, ax, h, result)                                         \
+  /* derivative along axis ax of h of element ee, evaluated at this point */
+#define LINE_DERIV(ee, ax, hh, result)                                        \
   do {                                                                        \
     int64_t st = 1;                                                           \
     for (int d = (ax) + 1; d < g.nd; ++d) st *= g.dims[d];                    \
     int64_t base = idx - (int64_t)ix[ax] * st;                                \
     const double *src = W + (int64_t)(ee) * E;                                \
-    for (int i = 0; i < g.dims[ax]; ++i) f[i] = src[base + i * st];           \
-    orc_deriv_line(g.dims[ax], (h), f, y);                                    \
+    for (int i = 0; i < g.dims[ax]; ++i) {                                    \
+      double qq[3], pp[3];                                                    \
+      point_coords(P, &g, base + i * st, qq, pp);                             \
+      f[i] = src[base + i * st] / sym_factor(P, qq, pp);                      \
+    }                                                                         \
+    orc_deriv_line(g.dims[ax], (hh), f, y);                                   \
     (result) = y[ix[ax]];                                                     \
   } while (0)
 
+  const double fac = sym_factor(P, q, p);
   double acc = 0.0, d;
   for (int s = 0; s < M; ++s) {
     LINE_DERIV(e, M + s, g.hp[s], d);
@@ -386,14 +435,15 @@ double orc_rhs_point(const orc_params *P, const double *W, int e, int64_t idx) {
   }
   double damp = 0.0;
   for (int s = 0; s < M; ++s) damp += n[s] * P->gamma[s];
-  acc -= damp * W[(int64_t)e * E + idx];
+  acc -= damp * W[(int64_t)e * E + idx] / fac;
   for (int s = 0; s < M; ++s) {
     int up[3] = {0, 0, 0};
     for (int t = 0; t < M; ++t) up[t] = n[t] + (t == s);
     int eu = find_element(nvec, ne, M, up);
     if (eu < 0) continue;
     LINE_DERIV(eu, M + s, g.hp[s], d);
-    acc += dV(P, s, q[s]) * d;
+    const double hu = W[(int64_t)eu * E + idx] / fac;
+    acc += dV(P, s, q[s]) * (d - P->beta / (2.0 * P->m[s]) * p[s] * hu);
   }
   for (int s = 0; s < M; ++s) {
     if (n[s] == 0) continue;
@@ -401,12 +451,12 @@ double orc_rhs_point(const orc_params *P, const double *W, int e, int64_t idx) {
     for (int t = 0; t < M; ++t) dn[t] = n[t] - (t == s);
     int ed = find_element(nvec, ne, M, dn);
     LINE_DERIV(ed, M + s, g.hp[s], d);
-    double v = dV(P, s, q[s]);
-    acc += n[s] * (P->m[s] * P->zeta[s] * P->gamma[s] / P->beta * v * d +
-                   P->zeta[s] * P->gamma[s] * p[s] * v * W[(int64_t)ed * E + idx]);
+    const double hd = W[(int64_t)ed * E + idx] / fac;
+    acc += n[s] * P->m[s] * P->zeta[s] * P->gamma[s] / P->beta * dV(P, s, q[s]) *
+           (d + P->beta / (2.0 * P->m[s]) * p[s] * hd);
   }
 #undef LINE_DERIV
-  return acc;
+  return acc * fac;
 }
 
 /* ------------------------------------------------------------------ */
@@ -487,27 +537,33 @@ void orc_equilibrate(const orc_params *P, double *W, int64_t nsteps, double dt) 
   orc_rk4(P, W, nsteps, dt);
 }
 
-/* (X^x W)_n = sum_s dX/dq_s dW_n/dp_s, for every element n */
+/* (X^x W)_n = sum_s dX/dq_s dW_n/dp_s for every element n; with W = exp(-beta H/2) h
+ * this is exp(-beta H/2) sum_s dX/dq_s (d/dp_s - beta p_s / 2 m_s) h_n */
 void orc_perturb(const orc_params *P, const orc_optical *X, const double *W, double *out) {
   geom g;
   make_geom(P, &g);
   int ne = orc_elements(P, NULL);
   double *tmp = (double *)malloc(sizeof(double) * g.E);
+  double *h = (double *)malloc(sizeof(double) * g.E * ne);
+  to_h(P, &g, ne, W, h);
   for (int e = 0; e < ne; ++e) {
-    const double *We = W + (int64_t)e * g.E;
+    const double *he = h + (int64_t)e * g.E;
     double *oe = out + (int64_t)e * g.E;
     memset(oe, 0, sizeof(double) * g.E);
     for (int s = 0; s < P->M; ++s) {
-      deriv_axis(g.dims, g.nd, P->M + s, g.hp[s], We, tmp);
+      deriv_axis(g.dims, g.nd, P->M + s, g.hp[s], he, tmp);
+      const double bm = P->beta / (2.0 * P->m[s]);
 #pragma omp parallel for schedule(static)
       for (int64_t i = 0; i < g.E; ++i) {
         double q[3], p[3];
         point_coords(P, &g, i, q, p);
-        oe[i] += orc_optical_grad(P, X, q, s) * tmp[i];
+        oe[i] += orc_optical_grad(P, X, q, s) * (tmp[i] - bm * p[s] * he[i]);
       }
     }
   }
+  from_h(P, &g, ne, out);
   free(tmp);
+  free(h);
 }
 
 /* <X>(W) = integral dq dp X(q) W_0(q, p) by the weighted midpoint rule */

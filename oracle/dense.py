@@ -4,9 +4,11 @@ The generator is built as a sparse matrix from the Kronecker form of the
 compact scheme (Sec. III B: (A_1 x I x I) dc/dq_1 = (B_1 x I x I) c, ...),
 with the printed matrices A (alpha on the off-diagonals) and B (a on the
 first, b on the second off-diagonals, antisymmetric) and the hierarchy
-couplings of Eq. (eq:HEOM).  The force dU/dq_s is taken from U itself by
-complex-step differentiation, so it does not reuse the oracle's hand-written
-derivative of the potential.  Only small grids are practical here.
+couplings of Eq. (eq:HEOM), acting on the smooth factor h_n of
+W_n = exp(-beta H/2) h_n (the factorization of Sec. III A).  The force
+dU/dq_s is taken from U itself by complex-step differentiation, so it does
+not reuse the oracle's hand-written derivative of the potential.  Only small
+grids are practical here.
 """
 from __future__ import annotations
 
@@ -69,12 +71,18 @@ def force(w: dict, q, s: int, eps: float = 1e-30):
     return np.imag(potential(w, qc)) / eps
 
 
-def generator(w: dict) -> sp.csr_matrix:
-    """Sparse matrix of the right-hand side of Eq. (eq:HEOM) on the grid."""
+def generator(w: dict, symmetrised: bool = True):
+    """(G, f): the sparse generator G acting on h (stacked elements) and the
+    factor f = exp(-beta H/2) on the grid, so that dW/dt = f * (G @ (W / f)).
+
+    With symmetrised=False the couplings of Eq. (eq:HEOM) are discretized on
+    W itself (G then acts on W and f = 1); kept to show that form is unstable.
+    """
     M, K = w["M"], w["K"]
     Nq, Np = list(w["Nq"]), list(w["Np"])
     dims = Nq + Np
     nd = 2 * M
+    beta = w["beta"]
     hq = [2.0 * w["Lq"][s] / Nq[s] for s in range(M)]
     hp = [2.0 * w["Lp"][s] / Np[s] for s in range(M)]
     axes = [grid(Nq[s], w["Lq"][s]) for s in range(M)] + [grid(Np[s], w["Lp"][s]) for s in range(M)]
@@ -105,16 +113,32 @@ def generator(w: dict) -> sp.csr_matrix:
         diag = diag - sum(n[s] * w["gamma"][s] for s in range(M)) * sp.identity(E)
         blocks[i][i] = diag
         for s in range(M):
+            bp = sp.diags(beta * p[s] / (2.0 * w["m"][s]))
+            c1 = w["m"][s] * w["zeta"][s] * w["gamma"][s] / beta
             up = tuple(n[t] + (t == s) for t in range(M))
             if up in index:
                 j = index[up]
-                blk = sp.diags(Vp[s]) @ Dp[s]
+                blk = sp.diags(Vp[s]) @ (Dp[s] - bp) if symmetrised else sp.diags(Vp[s]) @ Dp[s]
                 blocks[i][j] = blk if blocks[i][j] is None else blocks[i][j] + blk
             if n[s] > 0:
                 dn = tuple(n[t] - (t == s) for t in range(M))
                 j = index[dn]
-                c1 = w["m"][s] * w["zeta"][s] * w["gamma"][s] / w["beta"]
-                c2 = w["zeta"][s] * w["gamma"][s]
-                blk = n[s] * (sp.diags(c1 * Vp[s]) @ Dp[s] + sp.diags(c2 * p[s] * Vp[s]))
+                if symmetrised:
+                    blk = n[s] * c1 * (sp.diags(Vp[s]) @ (Dp[s] + bp))
+                else:
+                    c2 = w["zeta"][s] * w["gamma"][s]
+                    blk = n[s] * (sp.diags(c1 * Vp[s]) @ Dp[s] + sp.diags(c2 * p[s] * Vp[s]))
                 blocks[i][j] = blk if blocks[i][j] is None else blocks[i][j] + blk
-    return sp.bmat(blocks, format="csr")
+    G = sp.bmat(blocks, format="csr")
+    if not symmetrised:
+        return G, np.ones(len(els) * E)
+    H = potential(w, q) + sum(p[s] ** 2 / (2.0 * w["m"][s]) for s in range(M))
+    f = np.tile(np.exp(-0.5 * beta * H), len(els))
+    return G, f
+
+
+def apply(w: dict, W: np.ndarray) -> np.ndarray:
+    """dW/dt for a state W of the workload's shape."""
+    G, f = generator(w)
+    x = W.ravel()
+    return (f * (G @ (x / f))).reshape(W.shape)
