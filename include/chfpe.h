@@ -1,0 +1,200 @@
+/*
+ * chfpe.h -- C ABI of the MI355X (gfx950) solver for the multimode classical
+ * hierarchical Fokker-Planck equations (CHFPE) of Hoshino & Tanimura,
+ * "A Multimode Classical Hierarchical Fokker-Planck Equations Approach to
+ * Molecular Vibrations: Simulating Two-Dimensional Spectra".
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns an int status (CHFPE_OK = 0, negative on error)
+ *     unless stated otherwise; no C++ exception crosses this boundary.
+ *   - Validation of arguments happens on the host before any device call, so
+ *     CHFPE_EINVAL never leaves the device in a changed state.
+ *   - Units are dimensionless with k_B = 1.
+ *   - A state is the hierarchy W^(n)(q_1..q_M, p_1..p_M) of Eq. (eq:HEOM):
+ *     FP64, C order [n][q_1..q_M][p_1..p_M] (p_M fastest); elements n are
+ *     {n in N^M : |n| <= K} ordered by |n|, then lexicographically with n_1
+ *     largest first.  Grids are uniform and cell-centred:
+ *     x_i = -L + (i + 1/2) h, h = 2L/N.
+ *   - Discretization: the compact sixth-order first derivative of Sec. III B
+ *     (alpha = 1/3; weights 7/9 and 1/36 on the first and second
+ *     differences; zero values outside the box) acts on the smooth factor
+ *     h_n of W_n = exp(-beta H_sys/2) h_n, the factorization of Sec. III A,
+ *     along every q and p axis; time integration is classical RK4 with a
+ *     fixed step.  Device buffers hold h; the functions below exchange W.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ *   - All device work of a context runs on the stream given to chfpe_setup;
+ *     functions that return host data synchronize that stream first.
+ */
+#ifndef CHFPE_H
+#define CHFPE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CHFPE_OK = 0,
+  CHFPE_EINVAL = -1,     /* invalid argument or unsupported shape           */
+  CHFPE_ENOMEM = -2,     /* workspace too small or allocation failed        */
+  CHFPE_EDEVICE = -3,    /* a HIP runtime call failed                       */
+  CHFPE_ENONFINITE = -4, /* the propagated state became non-finite          */
+  CHFPE_ESTATE = -5      /* call out of order (e.g. response before eq.)    */
+};
+
+enum { CHFPE_FP64 = 0, CHFPE_FP32 = 1 };
+
+/*
+ * Model and discretisation.
+ *   U(q) = sum_s [ m_s omega_s^2 q_s^2 / 2 + g3_s q_s^3 / 3! + g4_s q_s^4 / 4! ]
+ *        + sum_{s<s'} [ g2_ss' q_s q_s' + (g21_ss' q_s^2 q_s' + g12_ss' q_s q_s'^2) / 6 ]
+ *     (Sec. II A, Eqs. (sec: Potenentials), (sec: Potential ss'); the quartic
+ *     term extends the on-site potential).  Only entries s < s' of the pair
+ *     matrices are read.
+ *   V_s(q_s) = V_LL_s q_s + V_SL_s q_s^2 / 2 (system-bath coupling, Sec. II A).
+ *   Drude bath per mode: zeta_s, gamma_s (Eq. (eq:drude)); beta = 1/T.
+ *   K: hierarchy depth, elements {n : |n| <= K} (Eq. (eq:HEOM)).
+ *   Nq/Np, Lq/Lp: points and half-width of the q_s and p_s axes.
+ *   precision: CHFPE_FP64 (the only value accepted by this build).
+ * Limits: 1 <= M <= 3, 0 <= K <= 12, 5 <= N <= 48 on every axis, all
+ * masses, beta, L > 0, one element below 2^31 points, and
+ * exp(-beta H_sys/2) representable (> 1e-150) everywhere on the grid.
+ */
+typedef struct {
+  int32_t M;
+  int32_t K;
+  int32_t Nq[3];
+  int32_t Np[3];
+  double Lq[3];
+  double Lp[3];
+  double m[3];
+  double omega[3];
+  double g3[3];
+  double g4[3];
+  double g2[3][3];
+  double g21[3][3];
+  double g12[3][3];
+  double V_LL[3];
+  double V_SL[3];
+  double zeta[3];
+  double gamma[3];
+  double beta;
+  int32_t precision;
+} chfpe_params;
+
+/* Optical operator X(q) = sum_s lin_s q_s + 1/2 sum_{s,s'} quad_ss' q_s q_s'
+ * (dipole mu or polarizability Pi, Eqs. (NLdip), (NLpol)). */
+typedef struct {
+  double lin[3];
+  double quad[3][3];
+} chfpe_optical;
+
+typedef struct chfpe_ctx chfpe_ctx;
+
+/* Bytes of device workspace chfpe_setup needs for these parameters (tables,
+ * eight state-sized buffers, reduction scratch), or 0 if the parameters are
+ * invalid.  The caller may allocate it (e.g. as a torch tensor) and pass it
+ * to chfpe_setup. */
+size_t chfpe_workspace_bytes(const chfpe_params *p);
+
+/* Validate parameters, build the grids and coefficient tables of the
+ * right-hand side of Eq. (eq:HEOM) on the host, and upload them once.
+ *   dev_workspace: device memory of at least chfpe_workspace_bytes(p) bytes
+ *     owned by the caller and kept alive until chfpe_destroy, or NULL to let
+ *     the library allocate (and free in chfpe_destroy).
+ *   hip_stream: a hipStream_t on the current device, or NULL for the null
+ *     stream.
+ *   out: receives the new context; untouched on error.
+ * Errors: EINVAL (bad parameters), ENOMEM (workspace too small or allocation
+ * failed), EDEVICE. */
+int chfpe_setup(const chfpe_params *p, void *dev_workspace, size_t ws_bytes, void *hip_stream,
+                chfpe_ctx **out);
+
+/* Equilibration (Sec. IV B): state <- W_0 = exp(-beta H_sys)/Z with
+ * Z = integral of exp(-beta H_sys) (weighted midpoint rule, weights 1 except
+ * 0.8 at both ends of every axis), W_{n != 0} = 0; then n_steps classical
+ * RK4 steps of size dt; the result is kept as the equilibrium W_eq used by
+ * the response functions.  n_steps >= 0, dt > 0 (dt may be 0 only when
+ * n_steps == 0).  ENONFINITE if the state overflows. */
+int chfpe_equilibrate(chfpe_ctx *ctx, int64_t n_steps, double dt);
+
+/* n_steps classical RK4 steps of Eq. (eq:HEOM) on the context's current
+ * state, in place.  ENONFINITE if the state became non-finite (it is then
+ * unspecified). */
+int chfpe_propagate(chfpe_ctx *ctx, int64_t n_steps, double dt);
+
+/* Linear response, Eq. (1Dresponse):
+ *   R[j] = integral A(q) W_0 of G(j * stride * dt) A^x W_eq,  j = 0..n_t-1,
+ * with A^x W = sum_s dA/dq_s dW/dp_s on every element (Eq. (Opticalexc)).
+ * R is a host array of n_t doubles.  Uses W_eq (ESTATE before
+ * chfpe_equilibrate or chfpe_use_state_as_equilibrium); overwrites the
+ * current state. */
+int chfpe_response_1d(chfpe_ctx *ctx, const chfpe_optical *A, int64_t n_t, int32_t stride,
+                      double dt, double *R);
+
+/* Second-order response, Eq. (2Dresponse), by the t1/t2 double loop of
+ * Sec. IV C:
+ *   R[j2 * n_t1 + j1] = integral C W_0 of
+ *       G(j2 * stride2 * dt) B^x G(j1 * stride1 * dt) A^x W_eq.
+ * R is a host array of n_t2 * n_t1 doubles (t1 fastest).  The response
+ * values are accumulated on the device and copied back once.  Uses W_eq;
+ * overwrites the current state. */
+int chfpe_response_2d(chfpe_ctx *ctx, const chfpe_optical *A, const chfpe_optical *B,
+                      const chfpe_optical *C, int64_t n_t1, int64_t n_t2, int32_t stride1,
+                      int32_t stride2, double dt, double *R);
+
+/* Number of values in a state: |{n : |n| <= K}| * prod_s Nq_s * Np_s. */
+int64_t chfpe_state_count(const chfpe_ctx *ctx);
+
+/* Copy the current state to / from a host array of chfpe_state_count
+ * doubles in the canonical layout above. */
+int chfpe_get_state(chfpe_ctx *ctx, double *host);
+int chfpe_set_state(chfpe_ctx *ctx, const double *host);
+
+/* Keep the current state as W_eq (lets a caller supply its own equilibrium). */
+int chfpe_use_state_as_equilibrium(chfpe_ctx *ctx);
+
+/* One evaluation of the right-hand side of Eq. (eq:HEOM) on the current
+ * state; the result replaces the current state. */
+int chfpe_rhs(chfpe_ctx *ctx);
+
+/* Current state <- X^x (current state), Eq. (Opticalexc), every element. */
+int chfpe_perturb(chfpe_ctx *ctx, const chfpe_optical *X);
+
+/* *value = integral X(q) W_0(q, p) dq dp of the current state (weighted
+ * midpoint rule as for Z above). */
+int chfpe_observe(chfpe_ctx *ctx, const chfpe_optical *X, double *value);
+
+/* Bandwidth reference: copy `bytes` bytes (a multiple of 16) from src to
+ * dst, both device pointers, with a plain streaming kernel on hip_stream. */
+int chfpe_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
+
+/* Per-kernel timing with HIP events on the context's stream: every
+ * `every`-th RK4 step (0 turns timing off) each launch of that step is
+ * bracketed by events.  chfpe_kernel_times reports, for each kernel kind,
+ * the number of timed launches and their mean duration in milliseconds and
+ * the kind's name; it synchronizes the stream.  Returns the number of kinds
+ * written (at most max_kinds). */
+int chfpe_set_kernel_timing(chfpe_ctx *ctx, int32_t every);
+int chfpe_kernel_times(chfpe_ctx *ctx, int32_t max_kinds, int64_t *counts, double *mean_ms,
+                       const char **names);
+
+/* Algorithmic bytes per launch of each kernel kind (same order and names as
+ * chfpe_kernel_times); returns the number of kinds written. */
+int chfpe_kernel_bytes(const chfpe_ctx *ctx, int32_t max_kinds, double *bytes,
+                       const char **names);
+
+/* Message of the last error on this context (or of the last failed
+ * chfpe_setup on this thread when ctx is NULL); never NULL. */
+const char *chfpe_last_error(const chfpe_ctx *ctx);
+
+/* Release the context and any memory the library allocated. */
+void chfpe_destroy(chfpe_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHFPE_H */

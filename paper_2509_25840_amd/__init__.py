@@ -1,0 +1,284 @@
+"""MI355X (gfx950) solver for the multimode classical hierarchical Fokker-Planck
+equations (CHFPE): Python binding of the C ABI in ``include/chfpe.h``.
+
+This module only marshals arguments: every step of the computation runs in
+the HIP kernels of ``libchfpe.so``.  PyTorch supplies device memory (the
+context workspace) and the stream.  Importing works without a GPU; creating
+a ``Solver`` needs the built library and a visible gfx950 device and raises
+otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = ["Params", "Optical", "Solver", "ChfpeError", "lib", "params_from_workload",
+           "optical_from_dict", "workspace_bytes", "stream_copy", "LIB_PATH"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libchfpe.so")
+
+CHFPE_OK, CHFPE_EINVAL, CHFPE_ENOMEM, CHFPE_EDEVICE, CHFPE_ENONFINITE, CHFPE_ESTATE = 0, -1, -2, -3, -4, -5
+CHFPE_FP64, CHFPE_FP32 = 0, 1
+_CODES = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONFINITE", -5: "ESTATE"}
+
+_d3 = ctypes.c_double * 3
+_d33 = (ctypes.c_double * 3) * 3
+_i3 = ctypes.c_int32 * 3
+
+
+class Params(ctypes.Structure):
+    """chfpe_params."""
+    _fields_ = [
+        ("M", ctypes.c_int32), ("K", ctypes.c_int32),
+        ("Nq", _i3), ("Np", _i3), ("Lq", _d3), ("Lp", _d3),
+        ("m", _d3), ("omega", _d3), ("g3", _d3), ("g4", _d3),
+        ("g2", _d33), ("g21", _d33), ("g12", _d33),
+        ("V_LL", _d3), ("V_SL", _d3), ("zeta", _d3), ("gamma", _d3),
+        ("beta", ctypes.c_double), ("precision", ctypes.c_int32),
+    ]
+
+
+class Optical(ctypes.Structure):
+    """chfpe_optical: X(q) = sum lin_s q_s + 1/2 sum quad_ss' q_s q_s'."""
+    _fields_ = [("lin", _d3), ("quad", _d33)]
+
+
+class ChfpeError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"chfpe error {code} ({_CODES.get(code, '?')}): {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libchfpe.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ChfpeError(CHFPE_EDEVICE, f"{LIB_PATH} is missing: run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER(Params)
+    O = ctypes.POINTER(Optical)
+    vp = ctypes.c_void_p
+    dp = ctypes.POINTER(ctypes.c_double)
+    i64 = ctypes.c_int64
+    i32 = ctypes.c_int32
+    L.chfpe_workspace_bytes.argtypes = [P]
+    L.chfpe_workspace_bytes.restype = ctypes.c_size_t
+    L.chfpe_setup.argtypes = [P, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.chfpe_setup.restype = ctypes.c_int
+    L.chfpe_equilibrate.argtypes = [vp, i64, ctypes.c_double]
+    L.chfpe_equilibrate.restype = ctypes.c_int
+    L.chfpe_propagate.argtypes = [vp, i64, ctypes.c_double]
+    L.chfpe_propagate.restype = ctypes.c_int
+    L.chfpe_response_1d.argtypes = [vp, O, i64, i32, ctypes.c_double, dp]
+    L.chfpe_response_1d.restype = ctypes.c_int
+    L.chfpe_response_2d.argtypes = [vp, O, O, O, i64, i64, i32, i32, ctypes.c_double, dp]
+    L.chfpe_response_2d.restype = ctypes.c_int
+    L.chfpe_state_count.argtypes = [vp]
+    L.chfpe_state_count.restype = i64
+    L.chfpe_get_state.argtypes = [vp, dp]
+    L.chfpe_get_state.restype = ctypes.c_int
+    L.chfpe_set_state.argtypes = [vp, dp]
+    L.chfpe_set_state.restype = ctypes.c_int
+    L.chfpe_use_state_as_equilibrium.argtypes = [vp]
+    L.chfpe_use_state_as_equilibrium.restype = ctypes.c_int
+    L.chfpe_rhs.argtypes = [vp]
+    L.chfpe_rhs.restype = ctypes.c_int
+    L.chfpe_perturb.argtypes = [vp, O]
+    L.chfpe_perturb.restype = ctypes.c_int
+    L.chfpe_observe.argtypes = [vp, O, dp]
+    L.chfpe_observe.restype = ctypes.c_int
+    L.chfpe_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    L.chfpe_stream_copy.restype = ctypes.c_int
+    L.chfpe_set_kernel_timing.argtypes = [vp, i32]
+    L.chfpe_set_kernel_timing.restype = ctypes.c_int
+    L.chfpe_kernel_times.argtypes = [vp, i32, ctypes.POINTER(i64), dp, ctypes.POINTER(ctypes.c_char_p)]
+    L.chfpe_kernel_times.restype = ctypes.c_int
+    L.chfpe_kernel_bytes.argtypes = [vp, i32, dp, ctypes.POINTER(ctypes.c_char_p)]
+    L.chfpe_kernel_bytes.restype = ctypes.c_int
+    L.chfpe_last_error.argtypes = [vp]
+    L.chfpe_last_error.restype = ctypes.c_char_p
+    L.chfpe_destroy.argtypes = [vp]
+    L.chfpe_destroy.restype = None
+    _lib = L
+    return L
+
+
+def params_from_workload(w: dict, precision: int = CHFPE_FP64) -> Params:
+    """chfpe_params from a workload dict (see ``workloads``)."""
+    p = Params()
+    M = int(w["M"])
+    p.M, p.K = M, int(w["K"])
+    for s in range(M):
+        p.Nq[s], p.Np[s] = int(w["Nq"][s]), int(w["Np"][s])
+        p.Lq[s], p.Lp[s] = float(w["Lq"][s]), float(w["Lp"][s])
+        p.m[s], p.omega[s] = float(w["m"][s]), float(w["omega"][s])
+        p.g3[s], p.g4[s] = float(w["g3"][s]), float(w["g4"][s])
+        p.V_LL[s], p.V_SL[s] = float(w["VLL"][s]), float(w["VSL"][s])
+        p.zeta[s], p.gamma[s] = float(w["zeta"][s]), float(w["gamma"][s])
+        for t in range(M):
+            p.g2[s][t] = float(w["g2"][s][t])
+            p.g21[s][t] = float(w["g21"][s][t])
+            p.g12[s][t] = float(w["g12"][s][t])
+    p.beta = float(w["beta"])
+    p.precision = int(precision)
+    return p
+
+
+def optical_from_dict(X: dict) -> Optical:
+    o = Optical()
+    for s, v in enumerate(X["lin"]):
+        o.lin[s] = float(v)
+    for s, row in enumerate(X["quad"]):
+        for t, v in enumerate(row):
+            o.quad[s][t] = float(v)
+    return o
+
+
+def workspace_bytes(p: Params) -> int:
+    return int(lib().chfpe_workspace_bytes(ctypes.byref(p)))
+
+
+def stream_copy(dst, src, nbytes: int, stream=None) -> None:
+    """Plain device copy kernel (bandwidth reference); dst/src are torch tensors."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    rc = lib().chfpe_stream_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                                 ctypes.c_size_t(nbytes), ctypes.c_void_p(s.cuda_stream))
+    if rc != 0:
+        raise ChfpeError(rc, "stream copy failed")
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Solver:
+    """One solver context: workspace allocated by torch on ``device``,
+    work issued on the current torch stream of that device."""
+
+    def __init__(self, params: Params, device: str = "cuda:0"):
+        import torch
+        L = lib()
+        if not torch.cuda.is_available():
+            raise ChfpeError(CHFPE_EDEVICE, "no GPU visible to torch")
+        self.device = torch.device(device)
+        nbytes = workspace_bytes(params)
+        if nbytes == 0:
+            ctx = ctypes.c_void_p()
+            rc = L.chfpe_setup(ctypes.byref(params), None, 0, None, ctypes.byref(ctx))
+            raise ChfpeError(rc, L.chfpe_last_error(None).decode())
+        with torch.cuda.device(self.device):
+            self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            self.stream = torch.cuda.current_stream(self.device)
+        base = self._ws.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self._ctx = ctypes.c_void_p()
+        rc = L.chfpe_setup(ctypes.byref(params), ctypes.c_void_p(aligned), ctypes.c_size_t(nbytes),
+                           ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._ctx))
+        if rc != 0:
+            raise ChfpeError(rc, L.chfpe_last_error(None).decode())
+        self.params = params
+        self.count = int(L.chfpe_state_count(self._ctx))
+
+    # -- helpers ---------------------------------------------------------------
+    def _check(self, rc: int):
+        if rc != 0:
+            raise ChfpeError(rc, lib().chfpe_last_error(self._ctx).decode())
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().chfpe_destroy(self._ctx)
+            self._ctx = None
+            self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- the C ABI ---------------------------------------------------------------
+    def equilibrate(self, n_steps: int, dt: float):
+        self._check(lib().chfpe_equilibrate(self._ctx, int(n_steps), float(dt)))
+
+    def propagate(self, n_steps: int, dt: float):
+        self._check(lib().chfpe_propagate(self._ctx, int(n_steps), float(dt)))
+
+    def response_1d(self, A: dict, n_t: int, stride: int, dt: float) -> np.ndarray:
+        R = np.empty(int(n_t))
+        o = optical_from_dict(A)
+        self._check(lib().chfpe_response_1d(self._ctx, ctypes.byref(o), int(n_t), int(stride), float(dt),
+                                            _dptr(R)))
+        return R
+
+    def response_2d(self, A: dict, B: dict, C: dict, n_t1: int, n_t2: int, stride1: int, stride2: int,
+                    dt: float) -> np.ndarray:
+        R = np.empty((int(n_t2), int(n_t1)))
+        oa, ob, oc = optical_from_dict(A), optical_from_dict(B), optical_from_dict(C)
+        self._check(lib().chfpe_response_2d(self._ctx, ctypes.byref(oa), ctypes.byref(ob), ctypes.byref(oc),
+                                            int(n_t1), int(n_t2), int(stride1), int(stride2), float(dt),
+                                            _dptr(R)))
+        return R
+
+    def get_state(self) -> np.ndarray:
+        out = np.empty(self.count)
+        self._check(lib().chfpe_get_state(self._ctx, _dptr(out)))
+        return out
+
+    def set_state(self, W) -> None:
+        a = np.ascontiguousarray(W, dtype=np.float64).ravel()
+        if a.size != self.count:
+            raise ValueError(f"state has {a.size} values, expected {self.count}")
+        self._check(lib().chfpe_set_state(self._ctx, _dptr(a)))
+
+    def use_state_as_equilibrium(self):
+        self._check(lib().chfpe_use_state_as_equilibrium(self._ctx))
+
+    def rhs(self):
+        self._check(lib().chfpe_rhs(self._ctx))
+
+    def perturb(self, X: dict):
+        o = optical_from_dict(X)
+        self._check(lib().chfpe_perturb(self._ctx, ctypes.byref(o)))
+
+    def observe(self, X: dict) -> float:
+        o = optical_from_dict(X)
+        v = ctypes.c_double()
+        self._check(lib().chfpe_observe(self._ctx, ctypes.byref(o), ctypes.byref(v)))
+        return v.value
+
+    def set_kernel_timing(self, every: int):
+        self._check(lib().chfpe_set_kernel_timing(self._ctx, int(every)))
+
+    def kernel_times(self) -> dict:
+        n = 16
+        counts = (ctypes.c_int64 * n)()
+        means = (ctypes.c_double * n)()
+        names = (ctypes.c_char_p * n)()
+        k = lib().chfpe_kernel_times(self._ctx, n, counts, means, names)
+        if k < 0:
+            self._check(k)
+        return {names[i].decode(): (int(counts[i]), float(means[i])) for i in range(k)}
+
+    def kernel_bytes(self) -> dict:
+        n = 16
+        b = (ctypes.c_double * n)()
+        names = (ctypes.c_char_p * n)()
+        k = lib().chfpe_kernel_bytes(self._ctx, n, b, names)
+        if k < 0:
+            self._check(k)
+        return {names[i].decode(): float(b[i]) for i in range(k)}

@@ -1,0 +1,1113 @@
+// Host side of the gfx950 CHFPE solver: the C ABI declared in include/chfpe.h.
+//
+// Device buffers hold h_n with W_n = exp(-beta H/2) h_n (Sec. III A); the
+// ABI exchanges W, converting with the separable factor
+// exp(-beta U(q)/2) exp(-sum_s beta p_s^2/4m_s).
+// A context owns (inside one device workspace) the coefficient tables of the
+// right-hand side of Eq. (eq:HEOM), the equilibrium W_eq, the t1-branch state
+// U of the double loop of Sec. IV C, and the buffers of classical RK4:
+// y (the propagated state), yacc (running sum of the RK4 combination), xa/xb
+// (stage inputs, alternating) and t (partial right-hand side).  One RK4 step
+// is four stages; a stage is one k_pblock launch followed by one (M <= 2) or
+// two (M = 3) k_qpass launches, the last of which applies the stage update.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "chfpe.h"
+#include "kernels.h"
+
+using namespace chfpe;
+
+namespace {
+
+thread_local std::string g_setup_error = "no error";
+
+constexpr int kPBlockThreads = 256;  // k_pblock workgroup size
+constexpr int kQThreadsMax = 512;    // largest k_qpass workgroup
+
+constexpr int kNumKinds = 9;
+enum Kind : int {
+  K_PBLOCK = 0,
+  K_QACC = 1,
+  K_QS1 = 2,
+  K_QS2 = 3,
+  K_QS3 = 4,
+  K_QS4 = 5,
+  K_OBSERVE = 6,
+  K_PERTURB = 7,
+  K_QOUT = 8
+};
+const char *kKindNames[kNumKinds] = {"pblock_rhs", "qpass_acc", "qpass_rk4_s1", "qpass_rk4_s2",
+                                     "qpass_rk4_s3", "qpass_rk4_s4", "observe", "perturb",
+                                     "qpass_out"};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Derived {
+  int M, K, ne;
+  int Nq[3], Np[3];
+  int Q, P;
+  long long E, S;  // points per element, values per state
+  std::vector<int> nvec;  // ne * M
+};
+
+bool derive(const chfpe_params *p, Derived &d, std::string &err) {
+  if (!p) {
+    err = "params is NULL";
+    return false;
+  }
+  if (p->M < 1 || p->M > 3) {
+    err = "M must be 1, 2 or 3";
+    return false;
+  }
+  if (p->K < 0 || p->K > 12) {
+    err = "K must be in [0, 12]";
+    return false;
+  }
+  if (p->precision != CHFPE_FP64) {
+    err = "only CHFPE_FP64 is supported by this build";
+    return false;
+  }
+  d.M = p->M;
+  d.K = p->K;
+  d.Q = 1;
+  d.P = 1;
+  for (int s = 0; s < p->M; ++s) {
+    if (p->Nq[s] < 5 || p->Nq[s] > kMaxAxis || p->Np[s] < 5 || p->Np[s] > kMaxAxis) {
+      err = "every axis needs 5 <= N <= 48 points";
+      return false;
+    }
+    if (!(p->Lq[s] > 0) || !(p->Lp[s] > 0) || !(p->m[s] > 0)) {
+      err = "box half-widths and masses must be positive";
+      return false;
+    }
+    d.Nq[s] = p->Nq[s];
+    d.Np[s] = p->Np[s];
+    d.Q *= p->Nq[s];
+    d.P *= p->Np[s];
+  }
+  if (!(p->beta > 0)) {
+    err = "beta must be positive";
+    return false;
+  }
+  const double *scal[] = {p->omega, p->g3, p->g4, p->V_LL, p->V_SL, p->zeta, p->gamma};
+  for (auto arr : scal)
+    for (int s = 0; s < p->M; ++s)
+      if (!std::isfinite(arr[s])) {
+        err = "non-finite model parameter";
+        return false;
+      }
+  for (int s = 0; s < p->M; ++s)
+    for (int t = 0; t < p->M; ++t)
+      if (!std::isfinite(p->g2[s][t]) || !std::isfinite(p->g21[s][t]) || !std::isfinite(p->g12[s][t])) {
+        err = "non-finite coupling parameter";
+        return false;
+      }
+  // hierarchy elements: |n| ascending, then n_1 largest first
+  d.nvec.clear();
+  std::vector<int> cur(d.M, 0);
+  for (int deg = 0; deg <= d.K; ++deg) {
+    // enumerate compositions of deg into M parts, lexicographically descending
+    std::vector<int> n(d.M, 0);
+    std::function<void(int, int)> rec = [&](int s, int left) {
+      if (s == d.M - 1) {
+        n[s] = left;
+        d.nvec.insert(d.nvec.end(), n.begin(), n.end());
+        return;
+      }
+      for (int v = left; v >= 0; --v) {
+        n[s] = v;
+        rec(s + 1, left - v);
+      }
+    };
+    rec(0, deg);
+  }
+  d.ne = (int)(d.nvec.size() / d.M);
+  if (d.ne > 4096) {
+    err = "too many hierarchy elements";
+    return false;
+  }
+  d.E = (long long)d.Q * d.P;
+  d.S = d.E * d.ne;
+  if (d.E >= (1LL << 31)) {
+    err = "one element must have fewer than 2^31 points";
+    return false;
+  }
+  return true;
+}
+
+// Workspace layout (byte offsets, 256-aligned).
+struct Layout {
+  size_t F, Vp, pm, pg, gA, gB, Cw, wp, sq, sp, up, dn, cc, tc, damp, partial, scal, flag;
+  size_t bufs[7];
+  size_t total;
+};
+constexpr int kPartials = 2048;
+
+Layout layout(const Derived &d) {
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes, 256);
+    return at;
+  };
+  L.F = take(sizeof(double) * 3 * d.Q);
+  L.Vp = take(sizeof(double) * 3 * kTab);
+  L.pm = take(sizeof(double) * 3 * kTab);
+  L.pg = take(sizeof(double) * 3 * kTab);
+  L.gA = take(sizeof(double) * 3 * d.Q);
+  L.gB = take(sizeof(double) * 3 * d.Q);
+  L.Cw = take(sizeof(double) * d.Q);
+  L.wp = take(sizeof(double) * d.P);
+  L.sq = take(sizeof(double) * d.Q);
+  L.sp = take(sizeof(double) * d.P);
+  L.up = take(sizeof(int) * 3 * d.ne);
+  L.dn = take(sizeof(int) * 3 * d.ne);
+  L.cc = take(sizeof(double) * 3 * d.ne);
+  L.tc = take(sizeof(double) * 3 * d.ne);
+  L.damp = take(sizeof(double) * d.ne);
+  L.partial = take(sizeof(double) * kPartials);
+  L.scal = take(sizeof(double) * 16);
+  L.flag = take(sizeof(int) * 16);
+  for (int i = 0; i < 7; ++i) L.bufs[i] = take(sizeof(double) * (size_t)d.S);
+  L.total = o;
+  return L;
+}
+
+struct Launch {
+  PBlock pb{};
+  size_t pb_lds = 0;
+  int pb_threads = 256, pb_nmax = 48;
+  // strided-axis passes of one stage: qa (three modes only, accumulates into
+  // t) then qf (applies the stage update); qx: the p_1 excitation pass of
+  // three modes.
+  QPass qa{}, qf{}, qx{};
+  bool has_qa = false, qf_two = false, has_qx = false;
+  int qa_threads = 0, qf_threads = 0, qx_threads = 0;
+  size_t qa_lds = 0, qf_lds = 0;
+  int qa_nmax = 48, qf_nmax = 48, qx_nmax = 48;
+};
+
+int pad8(int n) { return (n + 7) / 8 * 8; }
+
+int nmax_bucket(int n) {
+  return n <= 8 ? 8 : n <= 12 ? 12 : n <= 16 ? 16 : n <= 24 ? 24 : n <= 32 ? 32 : 48;
+}
+
+}  // namespace
+
+struct chfpe_ctx {
+  chfpe_params prm;
+  Derived d;
+  Layout L;
+  Launch ln;
+  Geom g;
+  Tabs tb;
+  hipStream_t stream = nullptr;
+  unsigned char *ws = nullptr;
+  bool own_ws = false;
+  double *F, *Vp, *pm, *pg, *gA, *gB, *Cw, *wp, *sq, *sp, *cc, *tc, *damp, *partial, *scal;
+  int *up, *dn, *flag;
+  double *weq, *u, *y, *yacc, *xa, *xb, *t;
+  bool has_eq = false;
+  double dV = 1.0;
+  std::vector<double> qgrid[3], pgrid[3];
+  std::vector<double> wq_host;  // q-point weights (product over q axes), Q entries
+  std::vector<double> sq_host;  // exp(-beta U(q)/2), Q entries
+  double *rbuf = nullptr;
+  size_t rbuf_cap = 0;
+  std::string err = "no error";
+  // kernel timing
+  int timing_every = 0;
+  long long step_counter = 0;
+  bool timing_now = false;
+  struct Pending {
+    hipEvent_t a, b;
+    int kind;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> event_pool;
+  long long kcount[kNumKinds] = {0};
+  double ktime[kNumKinds] = {0};
+};
+
+namespace {
+
+int fail(chfpe_ctx *c, int code, const std::string &msg) {
+  if (c)
+    c->err = msg;
+  else
+    g_setup_error = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                                  \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(ctx, CHFPE_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+double coord(int i, int N, double L) { return -L + (i + 0.5) * (2.0 * L / N); }
+double qw(int i, int N) { return (i == 0 || i == N - 1) ? 0.8 : 1.0; }
+
+// Host tables of the right-hand side (FP64).
+void build_tables(chfpe_ctx *c, std::vector<double> &F, std::vector<double> &Vp,
+                  std::vector<double> &pm, std::vector<double> &pg, std::vector<double> &sq,
+                  std::vector<double> &sp, std::vector<double> &wp, std::vector<int> &up,
+                  std::vector<int> &dn, std::vector<double> &cc, std::vector<double> &tc,
+                  std::vector<double> &damp) {
+  const chfpe_params &p = c->prm;
+  const Derived &d = c->d;
+  const int M = d.M;
+  for (int s = 0; s < M; ++s) {
+    c->qgrid[s].resize(d.Nq[s]);
+    c->pgrid[s].resize(d.Np[s]);
+    for (int i = 0; i < d.Nq[s]; ++i) c->qgrid[s][i] = coord(i, d.Nq[s], p.Lq[s]);
+    for (int i = 0; i < d.Np[s]; ++i) c->pgrid[s][i] = coord(i, d.Np[s], p.Lp[s]);
+  }
+  F.assign(3 * d.Q, 0.0);
+  sq.assign(d.Q, 0.0);
+  c->wq_host.assign(d.Q, 1.0);
+  for (int ql = 0; ql < d.Q; ++ql) {
+    double q[3] = {0, 0, 0};
+    int rem = ql;
+    double wgt = 1.0;
+    for (int s = M - 1; s >= 0; --s) {
+      const int j = rem % d.Nq[s];
+      rem /= d.Nq[s];
+      q[s] = c->qgrid[s][j];
+      wgt *= qw(j, d.Nq[s]);
+    }
+    c->wq_host[ql] = wgt;
+    double U = 0.0;
+    for (int s = 0; s < M; ++s) {
+      const double x = q[s], k2 = p.m[s] * p.omega[s] * p.omega[s];
+      U += 0.5 * k2 * x * x + p.g3[s] * x * x * x / 6.0 + p.g4[s] * x * x * x * x / 24.0;
+      F[s * d.Q + ql] = k2 * x + 0.5 * p.g3[s] * x * x + p.g4[s] * x * x * x / 6.0;
+    }
+    for (int s = 0; s < M; ++s)
+      for (int t = s + 1; t < M; ++t) {
+        const double a = q[s], b = q[t];
+        U += p.g2[s][t] * a * b + (p.g21[s][t] * a * a * b + p.g12[s][t] * a * b * b) / 6.0;
+        F[s * d.Q + ql] += p.g2[s][t] * b + (2.0 * p.g21[s][t] * a * b + p.g12[s][t] * b * b) / 6.0;
+        F[t * d.Q + ql] += p.g2[s][t] * a + (p.g21[s][t] * a * a + 2.0 * p.g12[s][t] * a * b) / 6.0;
+      }
+    sq[ql] = std::exp(-0.5 * p.beta * U);
+  }
+  c->sq_host = sq;
+  Vp.assign(3 * kTab, 0.0);
+  pm.assign(3 * kTab, 0.0);
+  pg.assign(3 * kTab, 0.0);
+  for (int s = 0; s < M; ++s) {
+    for (int j = 0; j < d.Nq[s]; ++j) Vp[s * kTab + j] = p.V_LL[s] + p.V_SL[s] * c->qgrid[s][j];
+    for (int j = 0; j < d.Np[s]; ++j) {
+      pg[s * kTab + j] = c->pgrid[s][j];
+      pm[s * kTab + j] = c->pgrid[s][j] / p.m[s];
+    }
+  }
+  sp.assign(d.P, 0.0);
+  wp.assign(d.P, 1.0);
+  for (int pi = 0; pi < d.P; ++pi) {
+    int rem = pi;
+    double ke = 0.0, wgt = 1.0;
+    for (int s = M - 1; s >= 0; --s) {
+      const int j = rem % d.Np[s];
+      rem /= d.Np[s];
+      const double x = c->pgrid[s][j];
+      ke += x * x / (2.0 * p.m[s]);
+      wgt *= qw(j, d.Np[s]);
+    }
+    sp[pi] = std::exp(-0.5 * p.beta * ke);
+    wp[pi] = wgt * sp[pi];  // quadrature weight times the p part of exp(-beta H/2)
+  }
+  const int ne = d.ne;
+  up.assign(3 * ne, -1);
+  dn.assign(3 * ne, -1);
+  cc.assign(3 * ne, 0.0);
+  tc.assign(3 * ne, 0.0);
+  damp.assign(ne, 0.0);
+  auto find = [&](const int *want) {
+    for (int e = 0; e < ne; ++e) {
+      bool ok = true;
+      for (int s = 0; s < M; ++s) ok = ok && d.nvec[e * M + s] == want[s];
+      if (ok) return e;
+    }
+    return -1;
+  };
+  for (int e = 0; e < ne; ++e) {
+    const int *n = &d.nvec[e * M];
+    for (int s = 0; s < M; ++s) {
+      damp[e] += n[s] * p.gamma[s];
+      int nb[3] = {0, 0, 0};
+      for (int t = 0; t < M; ++t) nb[t] = n[t] + (t == s ? 1 : 0);
+      up[e * 3 + s] = find(nb);
+      if (n[s] > 0) {
+        for (int t = 0; t < M; ++t) nb[t] = n[t] - (t == s ? 1 : 0);
+        dn[e * 3 + s] = find(nb);
+        cc[e * 3 + s] = n[s] * p.zeta[s] * p.gamma[s] * p.m[s] / p.beta;
+        tc[e * 3 + s] = n[s] * p.zeta[s] * p.gamma[s];
+      }
+    }
+  }
+}
+
+void make_geom(chfpe_ctx *c) {
+  const Derived &d = c->d;
+  Geom &g = c->g;
+  std::memset(&g, 0, sizeof(g));
+  g.M = d.M;
+  g.ne = d.ne;
+  g.Q = d.Q;
+  g.P = d.P;
+  g.E = d.E;
+  const int NpM = d.Np[d.M - 1];
+  int qs = 1, ps = 1;
+  for (int s = d.M - 1; s >= 0; --s) {
+    g.Nq[s] = d.Nq[s];
+    g.Np[s] = d.Np[s];
+    g.QS[s] = qs;
+    g.PS[s] = ps;
+    g.PSp[s] = (s == d.M - 1) ? 1 : ps / NpM * (NpM + 1);
+    qs *= d.Nq[s];
+    ps *= d.Np[s];
+  }
+  for (int s = 0; s < d.M; ++s) {
+    const double hq = 2.0 * c->prm.Lq[s] / d.Nq[s];
+    const double hp = 2.0 * c->prm.Lp[s] / d.Np[s];
+    g.bm[s] = c->prm.beta / (2.0 * c->prm.m[s]);
+    g.dq_ca[s] = 7.0 / 9.0 / hq;
+    g.dq_cb[s] = 1.0 / 36.0 / hq;
+    g.dp_ca[s] = 7.0 / 9.0 / hp;
+    g.dp_cb[s] = 1.0 / 36.0 / hp;
+  }
+  // dV = prod h
+  c->dV = 1.0;
+  for (int s = 0; s < d.M; ++s)
+    c->dV *= (2.0 * c->prm.Lq[s] / d.Nq[s]) * (2.0 * c->prm.Lp[s] / d.Np[s]);
+}
+
+// Axis ids: 0..M-1 are q_1..q_M, M..2M-1 are p_1..p_M.
+int axis_len(const Derived &d, int ax) { return ax < d.M ? d.Nq[ax] : d.Np[ax - d.M]; }
+int axis_stride(const Geom &g, int ax) { return ax < g.M ? g.QS[ax] * g.P : g.PS[ax - g.M]; }
+double axis_ca(const Geom &g, int ax) { return ax < g.M ? g.dq_ca[ax] : g.dp_ca[ax - g.M]; }
+double axis_cb(const Geom &g, int ax) { return ax < g.M ? g.dq_cb[ax] : g.dp_cb[ax - g.M]; }
+
+// Pass over axes a (and b), tiling the innermost contiguous run of length
+// `run` in chunks of pc; `rest` lists the remaining axes (outer first).
+QPass make_qpass(chfpe_ctx *c, int a, int b, int run, std::vector<int> rest, int pc) {
+  const Derived &d = c->d;
+  const Geom &g = c->g;
+  QPass q{};
+  q.a = a;
+  q.b = b;
+  q.sa_mode = a % d.M;
+  q.sb_mode = b >= 0 ? b % d.M : 0;
+  q.Na = axis_len(d, a);
+  q.Nb = b >= 0 ? axis_len(d, b) : 1;
+  q.sa = axis_stride(g, a);
+  q.sb = b >= 0 ? axis_stride(g, b) : 0;
+  q.run = run;
+  for (int i = 0; i < 3; ++i) {
+    q.rN[i] = 1;
+    q.rS[i] = 0;
+  }
+  const int nr = (int)rest.size();
+  for (int i = 0; i < nr; ++i) {  // right-align: the last rest axis goes to slot 2
+    q.rN[3 - nr + i] = axis_len(d, rest[i]);
+    q.rS[3 - nr + i] = axis_stride(g, rest[i]);
+  }
+  q.nrest = q.rN[0] * q.rN[1] * q.rN[2];
+  q.pc = std::min(pc, run);
+  q.nchunk = (run + q.pc - 1) / q.pc;
+  q.ntasks = d.ne * q.nrest * q.nchunk;
+  q.nblk = pad8(q.ntasks);
+  q.ca_a = axis_ca(g, a);
+  q.cb_a = axis_cb(g, a);
+  q.ca_b = b >= 0 ? axis_ca(g, b) : 0.0;
+  q.cb_b = b >= 0 ? axis_cb(g, b) : 0.0;
+  return q;
+}
+
+// two-axis tile: Na * Nb * pc values in LDS, max(Na, Nb) * pc threads
+void plan_two(chfpe_ctx *c, int a, int b, int run, std::vector<int> rest, QPass &out, int &thr,
+              size_t &lds, int &nmax) {
+  const Derived &d = c->d;
+  const int Na = axis_len(d, a), Nb = axis_len(d, b);
+  int pc = 16;
+  while (pc > 1 && ((size_t)Na * Nb * pc * sizeof(double) > 80 * 1024 || std::max(Na, Nb) * pc > kQThreadsMax))
+    pc /= 2;
+  out = make_qpass(c, a, b, run, rest, pc);
+  thr = (std::max(Na, Nb) * out.pc + 63) / 64 * 64;
+  lds = (size_t)Na * Nb * out.pc * sizeof(double);
+  nmax = nmax_bucket(std::max(Na, Nb));
+}
+
+void plan_one(chfpe_ctx *c, int a, int run, std::vector<int> rest, QPass &out, int &thr, int &nmax) {
+  out = make_qpass(c, a, -1, run, rest, 256);
+  thr = (out.pc + 63) / 64 * 64;
+  nmax = nmax_bucket(axis_len(c->d, a));
+}
+
+// Choose tile shapes.
+void plan(chfpe_ctx *c) {
+  const Derived &d = c->d;
+  Launch &ln = c->ln;
+  const int M = d.M;
+  const int NpM = d.Np[M - 1];
+  // k_pblock: the innermost one (one mode) or two p axes
+  PBlock &pb = ln.pb;
+  pb.NB = M == 1 ? 1 : 2;
+  pb.B = M == 1 ? d.Np[0] : d.Np[M - 2] * d.Np[M - 1];
+  pb.rows = pb.B / NpM;
+  pb.nblocks = (int)(d.E / pb.B);
+  const size_t blk_bytes = 2 * (size_t)pb.rows * (NpM + 1) * sizeof(double);  // G + ACC
+  int nb = std::max<int>(1, (int)((40 * 1024) / blk_bytes));
+  while (nb > 1 && (long long)nb * pb.B > 4096) --nb;
+  nb = std::min(nb, pb.nblocks);
+  pb.nb = nb;
+  pb.tileP = nb * pb.rows * (NpM + 1);
+  pb.ntasks = d.ne * ((pb.nblocks + nb - 1) / nb);
+  pb.nblk = pad8(pb.ntasks);
+  ln.pb_lds = (size_t)nb * blk_bytes;
+  ln.pb_threads = kPBlockThreads;
+  ln.pb_nmax = nmax_bucket(M == 1 ? d.Np[0] : std::max(d.Np[M - 2], d.Np[M - 1]));
+  // strided-axis passes
+  if (M == 1) {
+    ln.has_qa = false;
+    ln.qf_two = false;
+    plan_one(c, 0, d.P, {}, ln.qf, ln.qf_threads, ln.qf_nmax);
+    ln.qf_lds = 0;
+    ln.has_qx = false;
+  } else if (M == 2) {
+    ln.has_qa = false;
+    ln.qf_two = true;
+    plan_two(c, 0, 1, d.P, {}, ln.qf, ln.qf_threads, ln.qf_lds, ln.qf_nmax);
+    ln.has_qx = false;
+  } else {
+    // (q_2, q_3) over whole p-blocks, then (q_1, p_1) over (p_2, p_3) planes
+    const int plane = d.Np[1] * d.Np[2];
+    ln.has_qa = true;
+    plan_two(c, 1, 2, d.P, {0}, ln.qa, ln.qa_threads, ln.qa_lds, ln.qa_nmax);
+    ln.qf_two = true;
+    plan_two(c, 0, M + 0, plane, {1, 2}, ln.qf, ln.qf_threads, ln.qf_lds, ln.qf_nmax);
+    ln.has_qx = true;
+    plan_one(c, M + 0, plane, {0, 1, 2}, ln.qx, ln.qx_threads, ln.qx_nmax);
+  }
+}
+
+// --------------------------------------------------------------------------
+// kernel launch helpers (template dispatch on NMAX)
+// --------------------------------------------------------------------------
+
+hipEvent_t get_event(chfpe_ctx *c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+int drain_timing(chfpe_ctx *c) {
+  if (c->pending.empty()) return CHFPE_OK;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (auto &pd : c->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pd.a, pd.b) == hipSuccess) {
+      c->kcount[pd.kind] += 1;
+      c->ktime[pd.kind] += ms;
+    }
+    c->event_pool.push_back(pd.a);
+    c->event_pool.push_back(pd.b);
+  }
+  c->pending.clear();
+  return CHFPE_OK;
+}
+
+struct TimedScope {
+  chfpe_ctx *c;
+  int kind;
+  hipEvent_t a = nullptr;
+  TimedScope(chfpe_ctx *c_, int k) : c(c_), kind(k) {
+    if (c->timing_now) {
+      a = get_event(c);
+      if (a) (void)hipEventRecord(a, c->stream);
+    }
+  }
+  ~TimedScope() {
+    if (a) {
+      hipEvent_t b = get_event(c);
+      if (b) {
+        (void)hipEventRecord(b, c->stream);
+        c->pending.push_back({a, b, kind});
+      } else {
+        c->event_pool.push_back(a);
+      }
+    }
+  }
+};
+
+template <typename K>
+void allow_lds(K kern, size_t bytes) {
+  if (bytes > 64 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <int NMAX, bool PERTURB>
+void launch_pblock_n(chfpe_ctx *c, const double *X, double *out, const double *grad) {
+  const Launch &ln = c->ln;
+  auto kern = k_pblock<double, NMAX, PERTURB>;
+  allow_lds(kern, ln.pb_lds);
+  hipLaunchKernelGGL(kern, dim3(ln.pb.nblk), dim3(ln.pb_threads), ln.pb_lds, c->stream, c->g, c->tb, ln.pb,
+                     X, out, grad);
+}
+
+template <bool PERTURB>
+void launch_pblock_t(chfpe_ctx *c, const double *X, double *out, const double *grad) {
+  switch (c->ln.pb_nmax) {
+    case 8: launch_pblock_n<8, PERTURB>(c, X, out, grad); break;
+    case 12: launch_pblock_n<12, PERTURB>(c, X, out, grad); break;
+    case 16: launch_pblock_n<16, PERTURB>(c, X, out, grad); break;
+    case 24: launch_pblock_n<24, PERTURB>(c, X, out, grad); break;
+    case 32: launch_pblock_n<32, PERTURB>(c, X, out, grad); break;
+    default: launch_pblock_n<48, PERTURB>(c, X, out, grad); break;
+  }
+}
+
+template <int NMAX, bool TWO, int EPI, int FA, int FB>
+void launch_q_n(chfpe_ctx *c, const QPass &qp, int threads, size_t lds, const double *X, double *Tacc,
+                const double *y, double *yacc, double *xo, const double *grad, double dt) {
+  auto kern = k_qpass<double, NMAX, TWO, EPI, FA, FB>;
+  allow_lds(kern, lds);
+  hipLaunchKernelGGL(kern, dim3(qp.nblk), dim3(threads), lds, c->stream, c->g, c->tb, qp, X, Tacc, y,
+                     yacc, xo, grad, dt);
+}
+
+template <bool TWO, int EPI, int FA, int FB>
+void launch_q_t(chfpe_ctx *c, const QPass &qp, int threads, size_t lds, int nmax, const double *X,
+                double *Tacc, const double *y, double *yacc, double *xo, const double *grad, double dt) {
+  switch (nmax) {
+    case 8: launch_q_n<8, TWO, EPI, FA, FB>(c, qp, threads, lds, X, Tacc, y, yacc, xo, grad, dt); break;
+    case 12: launch_q_n<12, TWO, EPI, FA, FB>(c, qp, threads, lds, X, Tacc, y, yacc, xo, grad, dt); break;
+    case 16: launch_q_n<16, TWO, EPI, FA, FB>(c, qp, threads, lds, X, Tacc, y, yacc, xo, grad, dt); break;
+    case 24: launch_q_n<24, TWO, EPI, FA, FB>(c, qp, threads, lds, X, Tacc, y, yacc, xo, grad, dt); break;
+    case 32: launch_q_n<32, TWO, EPI, FA, FB>(c, qp, threads, lds, X, Tacc, y, yacc, xo, grad, dt); break;
+    default: launch_q_n<48, TWO, EPI, FA, FB>(c, qp, threads, lds, X, Tacc, y, yacc, xo, grad, dt); break;
+  }
+}
+
+// One right-hand-side evaluation of X fused with the stage update EPI.
+template <int EPI>
+void launch_stage(chfpe_ctx *c, const double *X, const double *y, double *yacc, double *xo, double dt) {
+  const Launch &ln = c->ln;
+  {
+    TimedScope ts(c, K_PBLOCK);
+    launch_pblock_t<false>(c, X, c->t, nullptr);
+  }
+  if (ln.has_qa) {
+    TimedScope ts(c, K_QACC);
+    launch_q_t<true, EPI_ACC, FQ, FQ>(c, ln.qa, ln.qa_threads, ln.qa_lds, ln.qa_nmax, X, c->t, nullptr,
+                                      nullptr, nullptr, nullptr, dt);
+  }
+  const int kind = EPI == EPI_S1 ? K_QS1 : EPI == EPI_S2 ? K_QS2 : EPI == EPI_S3 ? K_QS3
+                 : EPI == EPI_S4 ? K_QS4 : K_QOUT;
+  TimedScope ts(c, kind);
+  if (c->d.M == 1)
+    launch_q_t<false, EPI, FQ, FQ>(c, ln.qf, ln.qf_threads, 0, ln.qf_nmax, X, c->t, y, yacc, xo, nullptr, dt);
+  else if (c->d.M == 2)
+    launch_q_t<true, EPI, FQ, FQ>(c, ln.qf, ln.qf_threads, ln.qf_lds, ln.qf_nmax, X, c->t, y, yacc, xo,
+                                  nullptr, dt);
+  else
+    launch_q_t<true, EPI, FQ, FP>(c, ln.qf, ln.qf_threads, ln.qf_lds, ln.qf_nmax, X, c->t, y, yacc, xo,
+                                  nullptr, dt);
+}
+
+// out = X^x W for every element (grad: dX/dq_s table)
+void launch_perturb(chfpe_ctx *c, const double *W, double *out, const double *grad) {
+  TimedScope ts(c, K_PERTURB);
+  launch_pblock_t<true>(c, W, out, grad);
+  if (c->ln.has_qx)
+    launch_q_t<false, EPI_ACC, FX, FQ>(c, c->ln.qx, c->ln.qx_threads, 0, c->ln.qx_nmax, W, out, nullptr,
+                                       nullptr, nullptr, grad, 0.0);
+}
+
+int last_launch_error(chfpe_ctx *c) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, CHFPE_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+  return CHFPE_OK;
+}
+
+// n classical RK4 steps on buffer yb (in place).
+int rk4(chfpe_ctx *c, double *yb, long long nsteps, double dt) {
+  for (long long st = 0; st < nsteps; ++st) {
+    c->timing_now = c->timing_every > 0 && (c->step_counter % c->timing_every) == 0;
+    ++c->step_counter;
+    // stage 1: k1 = f(y); yacc = y + dt/6 k1; xa = y + dt/2 k1
+    launch_stage<EPI_S1>(c, yb, yb, c->yacc, c->xa, dt);
+    // stage 2: k2 = f(xa); yacc += dt/3 k2; xb = y + dt/2 k2
+    launch_stage<EPI_S2>(c, c->xa, yb, c->yacc, c->xb, dt);
+    // stage 3: k3 = f(xb); yacc += dt/3 k3; xa = y + dt k3
+    launch_stage<EPI_S3>(c, c->xb, yb, c->yacc, c->xa, dt);
+    // stage 4: k4 = f(xa); y = yacc + dt/6 k4
+    launch_stage<EPI_S4>(c, c->xa, nullptr, c->yacc, yb, dt);
+    if (c->timing_now) {
+      c->timing_now = false;
+      if (c->pending.size() > 4096) {
+        int rc = drain_timing(c);
+        if (rc) return rc;
+      }
+    }
+  }
+  return last_launch_error(c);
+}
+
+int observe_to(chfpe_ctx *c, const double *W, double *dst) {
+  TimedScope ts(c, K_OBSERVE);
+  const int nb = std::min(kPartials, std::max(1, (int)((c->d.E + 255) / 256)));
+  hipLaunchKernelGGL((k_reduce_w0<double>), dim3(nb), dim3(256), 0, c->stream, W, c->Cw, c->wp, c->d.Q,
+                     c->d.P, c->partial);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, c->stream, c->partial, nb, c->dV, dst);
+  return CHFPE_OK;
+}
+
+// upload grad tables (dX/dq_s on the q grid) for an optical operator
+void grad_table(chfpe_ctx *c, const chfpe_optical *X, std::vector<double> &out) {
+  const Derived &d = c->d;
+  out.assign(3 * d.Q, 0.0);
+  for (int ql = 0; ql < d.Q; ++ql) {
+    double q[3] = {0, 0, 0};
+    int rem = ql;
+    for (int s = d.M - 1; s >= 0; --s) {
+      q[s] = c->qgrid[s][rem % d.Nq[s]];
+      rem /= d.Nq[s];
+    }
+    for (int s = 0; s < d.M; ++s) {
+      double gv = X->lin[s];
+      for (int t = 0; t < d.M; ++t) gv += 0.5 * (X->quad[s][t] + X->quad[t][s]) * q[t];
+      out[s * d.Q + ql] = gv;
+    }
+  }
+}
+
+void value_table(chfpe_ctx *c, const chfpe_optical *X, std::vector<double> &out) {
+  const Derived &d = c->d;
+  out.assign(d.Q, 0.0);
+  for (int ql = 0; ql < d.Q; ++ql) {
+    double q[3] = {0, 0, 0};
+    int rem = ql;
+    for (int s = d.M - 1; s >= 0; --s) {
+      q[s] = c->qgrid[s][rem % d.Nq[s]];
+      rem /= d.Nq[s];
+    }
+    double v = 0.0;
+    for (int s = 0; s < d.M; ++s) {
+      v += X->lin[s] * q[s];
+      for (int t = 0; t < d.M; ++t) v += 0.5 * X->quad[s][t] * q[s] * q[t];
+    }
+    out[ql] = v * c->wq_host[ql] * c->sq_host[ql];
+  }
+}
+
+bool optical_ok(const chfpe_optical *X, int M) {
+  if (!X) return false;
+  for (int s = 0; s < M; ++s) {
+    if (!std::isfinite(X->lin[s])) return false;
+    for (int t = 0; t < M; ++t)
+      if (!std::isfinite(X->quad[s][t])) return false;
+  }
+  return true;
+}
+
+int check_finite(chfpe_ctx *c, const double *W) {
+  HIPCHK(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
+  hipLaunchKernelGGL((k_check_finite<double>), dim3(1024), dim3(256), 0, c->stream, W, c->d.S, c->flag);
+  int h = 0;
+  HIPCHK(c, hipMemcpyAsync(&h, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (h) return fail(c, CHFPE_ENONFINITE, "state became non-finite (dt above the RK4 stability limit?)");
+  return CHFPE_OK;
+}
+
+int ensure_rbuf(chfpe_ctx *c, size_t n) {
+  if (n <= c->rbuf_cap) return CHFPE_OK;
+  if (c->rbuf) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipFree(c->rbuf));
+    c->rbuf = nullptr;
+    c->rbuf_cap = 0;
+  }
+  HIPCHK(c, hipMalloc(&c->rbuf, n * sizeof(double)));
+  c->rbuf_cap = n;
+  return CHFPE_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+size_t chfpe_workspace_bytes(const chfpe_params *p) {
+  Derived d;
+  std::string err;
+  if (!derive(p, d, err)) return 0;
+  return layout(d).total;
+}
+
+int chfpe_setup(const chfpe_params *p, void *dev_workspace, size_t ws_bytes, void *hip_stream,
+                chfpe_ctx **out) {
+  if (!out) return fail(nullptr, CHFPE_EINVAL, "out is NULL");
+  Derived d;
+  std::string err;
+  if (!derive(p, d, err)) return fail(nullptr, CHFPE_EINVAL, err);
+  Layout L = layout(d);
+  if (dev_workspace && ws_bytes < L.total)
+    return fail(nullptr, CHFPE_ENOMEM, "workspace smaller than chfpe_workspace_bytes()");
+  if (dev_workspace && (reinterpret_cast<uintptr_t>(dev_workspace) % 256) != 0)
+    return fail(nullptr, CHFPE_EINVAL, "workspace must be 256-byte aligned");
+
+  chfpe_ctx *c = new chfpe_ctx();
+  c->prm = *p;
+  c->d = d;
+  c->L = L;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  if (dev_workspace) {
+    c->ws = reinterpret_cast<unsigned char *>(dev_workspace);
+  } else {
+    hipError_t e = hipMalloc(&c->ws, L.total);
+    if (e != hipSuccess) {
+      delete c;
+      return fail(nullptr, CHFPE_ENOMEM, std::string("hipMalloc workspace: ") + hipGetErrorString(e));
+    }
+    c->own_ws = true;
+  }
+  auto at = [&](size_t off) { return c->ws + off; };
+  c->F = (double *)at(L.F);
+  c->Vp = (double *)at(L.Vp);
+  c->pm = (double *)at(L.pm);
+  c->pg = (double *)at(L.pg);
+  c->gA = (double *)at(L.gA);
+  c->gB = (double *)at(L.gB);
+  c->Cw = (double *)at(L.Cw);
+  c->wp = (double *)at(L.wp);
+  c->sq = (double *)at(L.sq);
+  c->sp = (double *)at(L.sp);
+  c->up = (int *)at(L.up);
+  c->dn = (int *)at(L.dn);
+  c->cc = (double *)at(L.cc);
+  c->tc = (double *)at(L.tc);
+  c->damp = (double *)at(L.damp);
+  c->partial = (double *)at(L.partial);
+  c->scal = (double *)at(L.scal);
+  c->flag = (int *)at(L.flag);
+  double **bp[7] = {&c->weq, &c->u, &c->y, &c->yacc, &c->xa, &c->xb, &c->t};
+  for (int i = 0; i < 7; ++i) *bp[i] = (double *)at(L.bufs[i]);
+
+  make_geom(c);
+  std::vector<double> F, Vp, pm, pg, sq, sp, wp, cc, tc, damp;
+  std::vector<int> up, dn;
+  build_tables(c, F, Vp, pm, pg, sq, sp, wp, up, dn, cc, tc, damp);
+  {
+    double smin = 1.0;
+    for (double v : sq) smin = std::min(smin, v);
+    for (double v : sp) smin = std::min(smin, v);
+    if (!(smin > 1e-150)) {
+      chfpe_destroy(c);
+      return fail(nullptr, CHFPE_EINVAL, "box too large: exp(-beta H/2) underflows at its edge");
+    }
+  }
+  plan(c);
+
+  auto up_copy = [&](void *dst, const void *src, size_t bytes) {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream);
+  };
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = up_copy(c->F, F.data(), F.size() * sizeof(double));
+  if (e == hipSuccess) e = up_copy(c->Vp, Vp.data(), Vp.size() * sizeof(double));
+  if (e == hipSuccess) e = up_copy(c->pm, pm.data(), pm.size() * sizeof(double));
+  if (e == hipSuccess) e = up_copy(c->pg, pg.data(), pg.size() * sizeof(double));
+  if (e == hipSuccess) e = up_copy(c->sq, sq.data(), sq.size() * sizeof(double));
+  if (e == hipSuccess) e = up_copy(c->sp, sp.data(), sp.size() * sizeof(double));
+  if (e == hipSuccess) e = up_copy(c->wp, wp.data(), wp.size() * sizeof(double));
+  if (e == hipSuccess) e = up_copy(c->up, up.data(), up.size() * sizeof(int));
+  if (e == hipSuccess) e = up_copy(c->dn, dn.data(), dn.size() * sizeof(int));
+  if (e == hipSuccess) e = up_copy(c->cc, cc.data(), cc.size() * sizeof(double));
+  if (e == hipSuccess) e = up_copy(c->tc, tc.data(), tc.size() * sizeof(double));
+  if (e == hipSuccess) e = up_copy(c->damp, damp.data(), damp.size() * sizeof(double));
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // host vectors go out of scope
+  if (e != hipSuccess) {
+    std::string msg = std::string("table upload: ") + hipGetErrorString(e);
+    chfpe_destroy(c);
+    return fail(nullptr, CHFPE_EDEVICE, msg);
+  }
+  c->tb.F = c->F;
+  c->tb.Vp = c->Vp;
+  c->tb.pm = c->pm;
+  c->tb.pg = c->pg;
+  c->tb.up = c->up;
+  c->tb.dn = c->dn;
+  c->tb.cc = c->cc;
+  c->tb.tc = c->tc;
+  c->tb.damp = c->damp;
+  *out = c;
+  return CHFPE_OK;
+}
+
+int chfpe_equilibrate(chfpe_ctx *c, int64_t n_steps, double dt) {
+  if (!c) return CHFPE_EINVAL;
+  if (n_steps < 0 || !std::isfinite(dt) || (n_steps > 0 && !(dt > 0)))
+    return fail(c, CHFPE_EINVAL, "need n_steps >= 0 and dt > 0");
+  const int nb = 1024;
+  hipLaunchKernelGGL((k_boltzmann<double>), dim3(nb), dim3(256), 0, c->stream, c->y, c->sq, c->sp, c->d.Q,
+                     c->d.P, c->d.S);
+  // Z = dV sum w exp(-beta H) = dV sum (w_q sq)(w_p sp) h_0 with h_0 = sq sp
+  std::vector<double> ones(c->d.Q);
+  for (int ql = 0; ql < c->d.Q; ++ql) ones[ql] = c->wq_host[ql] * c->sq_host[ql];
+  HIPCHK(c, hipMemcpyAsync(c->Cw, ones.data(), ones.size() * sizeof(double), hipMemcpyHostToDevice,
+                           c->stream));
+  {
+    const int nbr = std::min(kPartials, std::max(1, (int)((c->d.E + 255) / 256)));
+    hipLaunchKernelGGL((k_reduce_w0<double>), dim3(nbr), dim3(256), 0, c->stream, c->y, c->Cw, c->wp,
+                       c->d.Q, c->d.P, c->partial);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, c->stream, c->partial, nbr, 1.0, c->scal);
+    hipLaunchKernelGGL((k_normalise<double>), dim3(1024), dim3(256), 0, c->stream, c->y, c->scal, c->dV,
+                       (int)c->d.E);
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));  // `ones` is read by the async copy
+  int rc = rk4(c, c->y, n_steps, dt);
+  if (rc) return rc;
+  rc = check_finite(c, c->y);
+  if (rc) return rc;
+  HIPCHK(c, hipMemcpyAsync(c->weq, c->y, c->d.S * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  c->has_eq = true;
+  return last_launch_error(c);
+}
+
+int chfpe_propagate(chfpe_ctx *c, int64_t n_steps, double dt) {
+  if (!c) return CHFPE_EINVAL;
+  if (n_steps < 0 || !std::isfinite(dt) || (n_steps > 0 && !(dt > 0)))
+    return fail(c, CHFPE_EINVAL, "need n_steps >= 0 and dt > 0");
+  int rc = rk4(c, c->y, n_steps, dt);
+  if (rc) return rc;
+  return check_finite(c, c->y);
+}
+
+int chfpe_rhs(chfpe_ctx *c) {
+  if (!c) return CHFPE_EINVAL;
+  launch_stage<EPI_OUT>(c, c->y, nullptr, nullptr, c->xa, 0.0);
+  std::swap(c->y, c->xa);
+  return last_launch_error(c);
+}
+
+int chfpe_perturb(chfpe_ctx *c, const chfpe_optical *X) {
+  if (!c) return CHFPE_EINVAL;
+  if (!optical_ok(X, c->d.M)) return fail(c, CHFPE_EINVAL, "invalid optical operator");
+  std::vector<double> gt;
+  grad_table(c, X, gt);
+  HIPCHK(c, hipMemcpyAsync(c->gA, gt.data(), gt.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  launch_perturb(c, c->y, c->xa, c->gA);
+  std::swap(c->y, c->xa);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return last_launch_error(c);
+}
+
+int chfpe_observe(chfpe_ctx *c, const chfpe_optical *X, double *value) {
+  if (!c || !value) return CHFPE_EINVAL;
+  if (!optical_ok(X, c->d.M)) return fail(c, CHFPE_EINVAL, "invalid optical operator");
+  std::vector<double> ct;
+  value_table(c, X, ct);
+  HIPCHK(c, hipMemcpyAsync(c->Cw, ct.data(), ct.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  observe_to(c, c->y, c->scal + 1);
+  HIPCHK(c, hipMemcpyAsync(value, c->scal + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return last_launch_error(c);
+}
+
+int chfpe_response_1d(chfpe_ctx *c, const chfpe_optical *A, int64_t n_t, int32_t stride, double dt,
+                      double *R) {
+  if (!c) return CHFPE_EINVAL;
+  if (!optical_ok(A, c->d.M) || n_t < 0 || stride < 0 || (n_t > 1 && stride < 1) || !R ||
+      !std::isfinite(dt) || (n_t > 1 && !(dt > 0)))
+    return fail(c, CHFPE_EINVAL, "invalid response arguments");
+  if (!c->has_eq) return fail(c, CHFPE_ESTATE, "no equilibrium: call chfpe_equilibrate first");
+  if (n_t == 0) return CHFPE_OK;
+  int rc = ensure_rbuf(c, (size_t)n_t);
+  if (rc) return rc;
+  std::vector<double> gt, ct;
+  grad_table(c, A, gt);
+  value_table(c, A, ct);
+  HIPCHK(c, hipMemcpyAsync(c->gA, gt.data(), gt.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->Cw, ct.data(), ct.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  launch_perturb(c, c->weq, c->y, c->gA);
+  for (int64_t j = 0; j < n_t; ++j) {
+    if (j > 0) {
+      rc = rk4(c, c->y, stride, dt);
+      if (rc) return rc;
+    }
+    observe_to(c, c->y, c->rbuf + j);
+  }
+  HIPCHK(c, hipMemcpyAsync(R, c->rbuf, n_t * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  rc = last_launch_error(c);
+  if (rc) return rc;
+  for (int64_t j = 0; j < n_t; ++j)
+    if (!std::isfinite(R[j])) return fail(c, CHFPE_ENONFINITE, "response became non-finite");
+  return CHFPE_OK;
+}
+
+int chfpe_response_2d(chfpe_ctx *c, const chfpe_optical *A, const chfpe_optical *B, const chfpe_optical *C,
+                      int64_t n_t1, int64_t n_t2, int32_t stride1, int32_t stride2, double dt, double *R) {
+  if (!c) return CHFPE_EINVAL;
+  if (!optical_ok(A, c->d.M) || !optical_ok(B, c->d.M) || !optical_ok(C, c->d.M) || n_t1 < 0 || n_t2 < 0 ||
+      stride1 < 0 || stride2 < 0 || (n_t1 > 1 && stride1 < 1) || (n_t2 > 1 && stride2 < 1) || !R ||
+      !std::isfinite(dt) || ((n_t1 > 1 || n_t2 > 1) && !(dt > 0)))
+    return fail(c, CHFPE_EINVAL, "invalid response arguments");
+  if (!c->has_eq) return fail(c, CHFPE_ESTATE, "no equilibrium: call chfpe_equilibrate first");
+  const int64_t n = n_t1 * n_t2;
+  if (n == 0) return CHFPE_OK;
+  int rc = ensure_rbuf(c, (size_t)n);
+  if (rc) return rc;
+  std::vector<double> ga, gb, ct;
+  grad_table(c, A, ga);
+  grad_table(c, B, gb);
+  value_table(c, C, ct);
+  HIPCHK(c, hipMemcpyAsync(c->gA, ga.data(), ga.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->gB, gb.data(), gb.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->Cw, ct.data(), ct.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  // U = A^x W_eq
+  launch_perturb(c, c->weq, c->u, c->gA);
+  for (int64_t j1 = 0; j1 < n_t1; ++j1) {
+    if (j1 > 0) {
+      rc = rk4(c, c->u, stride1, dt);
+      if (rc) return rc;
+    }
+    // V = B^x U
+    launch_perturb(c, c->u, c->y, c->gB);
+    for (int64_t j2 = 0; j2 < n_t2; ++j2) {
+      if (j2 > 0) {
+        rc = rk4(c, c->y, stride2, dt);
+        if (rc) return rc;
+      }
+      observe_to(c, c->y, c->rbuf + j2 * n_t1 + j1);
+    }
+  }
+  HIPCHK(c, hipMemcpyAsync(R, c->rbuf, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  rc = last_launch_error(c);
+  if (rc) return rc;
+  for (int64_t j = 0; j < n; ++j)
+    if (!std::isfinite(R[j])) return fail(c, CHFPE_ENONFINITE, "response became non-finite");
+  return CHFPE_OK;
+}
+
+int64_t chfpe_state_count(const chfpe_ctx *c) { return c ? c->d.S : 0; }
+
+int chfpe_get_state(chfpe_ctx *c, double *host) {
+  if (!c || !host) return CHFPE_EINVAL;
+  // W = exp(-beta H/2) h, converted in a scratch buffer
+  HIPCHK(c, hipMemcpyAsync(c->xb, c->y, c->d.S * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  hipLaunchKernelGGL((k_sym_scale<double>), dim3(1024), dim3(256), 0, c->stream, c->xb, c->sq, c->sp, c->d.Q,
+                     c->d.P, c->d.S, 1);
+  HIPCHK(c, hipMemcpyAsync(host, c->xb, c->d.S * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return last_launch_error(c);
+}
+
+int chfpe_set_state(chfpe_ctx *c, const double *host) {
+  if (!c || !host) return CHFPE_EINVAL;
+  HIPCHK(c, hipMemcpyAsync(c->y, host, c->d.S * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  hipLaunchKernelGGL((k_sym_scale<double>), dim3(1024), dim3(256), 0, c->stream, c->y, c->sq, c->sp, c->d.Q,
+                     c->d.P, c->d.S, 0);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return last_launch_error(c);
+}
+
+int chfpe_use_state_as_equilibrium(chfpe_ctx *c) {
+  if (!c) return CHFPE_EINVAL;
+  HIPCHK(c, hipMemcpyAsync(c->weq, c->y, c->d.S * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  c->has_eq = true;
+  return CHFPE_OK;
+}
+
+int chfpe_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream) {
+  if (!dst || !src || (bytes % 16) != 0) return CHFPE_EINVAL;
+  const long long n16 = (long long)(bytes / 16);
+  hipLaunchKernelGGL(k_stream_copy, dim3(4096), dim3(256), 0, reinterpret_cast<hipStream_t>(hip_stream),
+                     reinterpret_cast<uint4 *>(dst), reinterpret_cast<const uint4 *>(src), n16);
+  return hipGetLastError() == hipSuccess ? CHFPE_OK : CHFPE_EDEVICE;
+}
+
+int chfpe_set_kernel_timing(chfpe_ctx *c, int32_t every) {
+  if (!c || every < 0) return CHFPE_EINVAL;
+  c->timing_every = every;
+  c->step_counter = 0;
+  return CHFPE_OK;
+}
+
+int chfpe_kernel_times(chfpe_ctx *c, int32_t max_kinds, int64_t *counts, double *mean_ms,
+                       const char **names) {
+  if (!c) return CHFPE_EINVAL;
+  int rc = drain_timing(c);
+  if (rc) return rc;
+  int n = std::min<int>(max_kinds, kNumKinds);
+  for (int i = 0; i < n; ++i) {
+    if (counts) counts[i] = c->kcount[i];
+    if (mean_ms) mean_ms[i] = c->kcount[i] ? c->ktime[i] / c->kcount[i] : 0.0;
+    if (names) names[i] = kKindNames[i];
+  }
+  return n;
+}
+
+int chfpe_kernel_bytes(const chfpe_ctx *c, int32_t max_kinds, double *bytes, const char **names) {
+  if (!c) return CHFPE_EINVAL;
+  const double S = (double)c->d.S * sizeof(double);
+  const double E0 = (double)c->d.E * sizeof(double);
+  // each kernel's own inputs read once and outputs written once
+  const double b[kNumKinds] = {
+      2 * S,   // pblock_rhs: X -> t
+      3 * S,   // qpass_acc: X, t -> t
+      4 * S,   // s1: X(=y), t -> yacc, xa
+      6 * S,   // s2: X, t, y, yacc -> yacc, xb
+      6 * S,   // s3
+      4 * S,   // s4: X, t, yacc -> y
+      E0,      // observe: element 0
+      2 * S,   // pblock_perturb
+      3 * S};  // qpass_out: X, t -> out
+  int n = std::min<int>(max_kinds, kNumKinds);
+  for (int i = 0; i < n; ++i) {
+    if (bytes) bytes[i] = b[i];
+    if (names) names[i] = kKindNames[i];
+  }
+  return n;
+}
+
+const char *chfpe_last_error(const chfpe_ctx *c) { return c ? c->err.c_str() : g_setup_error.c_str(); }
+
+void chfpe_destroy(chfpe_ctx *c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto &pd : c->pending) {
+    (void)hipEventDestroy(pd.a);
+    (void)hipEventDestroy(pd.b);
+  }
+  for (auto ev : c->event_pool) (void)hipEventDestroy(ev);
+  if (c->rbuf) (void)hipFree(c->rbuf);
+  if (c->own_ws && c->ws) (void)hipFree(c->ws);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,556 @@
+// Device code of the gfx950 CHFPE solver.
+//
+// Every state buffer holds the smooth factor h_n of W_n = exp(-beta H/2) h_n
+// (the factorization of Sec. III A).  In h the hierarchy, Eq. (eq:HEOM), reads
+//   dh_n/dt = L h_n - sum_s n_s gamma_s h_n
+//           + sum_s V_s' (d/dp_s - beta p_s/2m_s) h_{n+e_s}
+//           + sum_s n_s (m_s zeta_s gamma_s/beta) V_s' (d/dp_s + beta p_s/2m_s) h_{n-e_s},
+// L h = sum_s F_s dh/dp_s - (p_s/m_s) dh/dq_s.
+// The right-hand side is split by axis family so that every compact
+// derivative (Sec. III B) sees whole lines:
+//
+//   k_pblock  -- for every element n and a run of q points, the whole
+//                p-block (all p_1..p_M values, contiguous in memory) is staged
+//                through LDS.  It forms the field the p_s derivative acts on,
+//                  G_{n,s} = F_s W_n + V_s' W_{n+e_s} + n_s zeta_s gamma_s (m_s/beta) V_s' W_{n-e_s},
+//                solves every p_s line (Thomas, line held in registers) and
+//                adds the pointwise terms
+//                  sum_s V_s' p_s [ (n_s zeta_s gamma_s/2) h_{n-e_s} - (beta/2m_s) h_{n+e_s} ]
+//                  - sum_s n_s gamma_s h_n.
+//                D_p(F W) = F D_p W and D_p(V' W) = V' D_p W because F_s and
+//                V_s' do not depend on p_s, so one solve per (n, s) covers the
+//                Liouvillian, Phi and the derivative part of Theta.
+//   k_qpass   -- the -(p_s/m_s) D_{q_s} W_n terms.  A tile is one or two
+//                q axes at full length times a chunk of consecutive p-block
+//                positions; each thread holds one q_a line in registers, a
+//                second q_b axis goes through LDS.  The last q pass of a
+//                stage also applies the classical RK4 stage update.
+//
+// All state arithmetic is in the template type T (double here); tables and
+// reductions are FP64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace chfpe {
+
+constexpr int kMaxAxis = 48;      // longest supported axis
+constexpr int kTab = 48;          // per-mode stride of 1-D tables
+
+// ---------------------------------------------------------------------------
+// Thomas factors of the constant tridiagonal matrix tridiag(1/3, 1, 1/3).
+// The forward factors do not depend on the line length (the first row is
+// [1, 1/3] for every N), so one table serves every axis.
+// ---------------------------------------------------------------------------
+struct ThomasTable {
+  double cp[kMaxAxis];   // super-diagonal after elimination
+  double inv[kMaxAxis];  // 1 / pivot
+};
+
+constexpr ThomasTable make_thomas() {
+  ThomasTable t{};
+  const double alpha = 1.0 / 3.0;
+  t.cp[0] = alpha;
+  t.inv[0] = 1.0;
+  for (int i = 1; i < kMaxAxis; ++i) {
+    const double piv = 1.0 - alpha * t.cp[i - 1];
+    t.inv[i] = 1.0 / piv;
+    t.cp[i] = alpha / piv;
+  }
+  return t;
+}
+
+constexpr ThomasTable kThomas = make_thomas();
+
+// Compact sixth-order first derivative of one line held in registers.
+// On entry f[0..N) holds the line and f[N..NMAX) must be zero (values beyond
+// the box are zero); on exit f[0..N) holds the derivative.
+//   (1/3) f'_{i-1} + f'_i + (1/3) f'_{i+1}
+//       = ca (f_{i+1} - f_{i-1}) + cb (f_{i+2} - f_{i-2}),  ca = 7/(9h), cb = 1/(36h).
+template <typename T, int NMAX>
+__device__ __forceinline__ void compact_deriv(T (&f)[NMAX], const int N, const T ca, const T cb) {
+  constexpr T third = T(1.0 / 3.0);
+  T d[NMAX];
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i) {
+    if (i < N) {
+      const T fm1 = (i >= 1) ? f[i >= 1 ? i - 1 : 0] : T(0);
+      const T fm2 = (i >= 2) ? f[i >= 2 ? i - 2 : 0] : T(0);
+      const T fp1 = (i + 1 < NMAX) ? f[i + 1 < NMAX ? i + 1 : NMAX - 1] : T(0);
+      const T fp2 = (i + 2 < NMAX) ? f[i + 2 < NMAX ? i + 2 : NMAX - 1] : T(0);
+      const T r = ca * (fp1 - fm1) + cb * (fp2 - fm2);
+      if (i == 0)
+        d[0] = r;
+      else
+        d[i] = (r - third * d[i >= 1 ? i - 1 : 0]) * T(kThomas.inv[i]);
+    }
+  }
+#pragma unroll
+  for (int i = NMAX - 1; i >= 0; --i) {
+    if (i < N) {
+      if (i == N - 1)
+        f[i] = d[i];
+      else
+        f[i] = d[i] - T(kThomas.cp[i]) * f[i + 1 < NMAX ? i + 1 : NMAX - 1];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Geometry and tables passed by value to every kernel.
+// ---------------------------------------------------------------------------
+struct Geom {
+  int M;         // modes
+  int ne;        // hierarchy elements
+  int Nq[3], Np[3];
+  int Q;         // prod Nq
+  int P;         // prod Np (one p-block)
+  int QS[3];     // stride of q_s in the q-linear index
+  int PS[3];     // stride of p_s inside a p-block
+  int PSp[3];    // same stride in the LDS layout (one pad value per p_M row)
+  long long E;   // points per element = Q * P
+  double dq_ca[3], dq_cb[3];  // 7/(9 h), 1/(36 h) for q_s
+  double dp_ca[3], dp_cb[3];  // same for p_s
+  double bm[3];               // beta / (2 m_s)
+};
+
+struct Tabs {
+  const double *F;      // [s][qlin]  dU/dq_s
+  const double *Vp;     // [s][j]     V_s'(q_s,j)          (stride kTab)
+  const double *pm;     // [s][j]     p_s,j / m_s          (stride kTab)
+  const double *pg;     // [s][j]     p_s,j                (stride kTab)
+  const int *up;        // [e][s]     index of n + e_s or -1
+  const int *dn;        // [e][s]     index of n - e_s or -1
+  const double *cc;     // [e][s]     n_s zeta_s gamma_s m_s / beta
+  const double *tc;     // [e][s]     n_s zeta_s gamma_s
+  const double *damp;   // [e]        sum_s n_s gamma_s
+};
+
+// Consecutive workgroup ids are dispatched round-robin over the 8 XCDs.
+// Give each XCD a contiguous range of tasks so that tasks touching the same
+// data (all elements of one q run) share that XCD's L2.  nblk is a multiple
+// of 8 chosen by the host.
+__device__ __forceinline__ int xcd_task(const int bid, const int nblk) {
+  const int per = nblk >> 3;
+  return (bid & 7) * per + (bid >> 3);
+}
+
+// ---------------------------------------------------------------------------
+// Tile descriptions passed by value.
+// ---------------------------------------------------------------------------
+// k_pblock: the innermost NB p axes (NB = 1 for one mode, else 2) form a
+// contiguous block of B values; a task is one element and a run of nb
+// consecutive blocks.  G (the field being differentiated) and ACC (the
+// partial right-hand side) live in LDS with one pad value per p_M row.
+struct PBlock {
+  int NB;            // p axes inside a block
+  int B;             // values per block
+  int rows;          // B / Np[M-1]
+  int nb;            // blocks per task
+  int nblocks;       // blocks per element (E / B)
+  int tileP;         // padded values of one LDS array
+  int ntasks, nblk;
+};
+
+// Field of a strided-axis line pass.
+enum Field : int {
+  FQ = 0,  // W_n along q_s, coefficient -p_s/m_s
+  FP = 1,  // G_{n,s} = F_s W_n + V_s'(W_{n+e_s} + cc W_{n-e_s}) along p_s, coefficient 1
+  FX = 2   // dX/dq_s W_n along p_s (optical excitation), coefficient 1
+};
+
+// k_qpass: a tile is one element, full lines along axis a (one per thread,
+// in registers) and optionally axis b (through LDS), times pc consecutive
+// positions of the innermost contiguous run (length `run`), with all other
+// indices fixed.  Axis ids: 0..M-1 are q_1..q_M, M..2M-1 are p_1..p_M.
+struct QPass {
+  int a, b;                 // axis ids; b < 0 for a single-axis pass
+  int sa_mode, sb_mode;     // mode index s of axes a and b
+  int Na, Nb;
+  int sa, sb;               // strides within an element
+  int run;                  // length of the contiguous run the chunks tile
+  int nrest;                // combinations of the remaining outer indices
+  int rN[3];                // their lengths (outer first)
+  int rS[3];                // their strides within an element
+  int pc;                   // run positions per tile
+  int nchunk;               // tiles per run
+  int ntasks, nblk;
+  double ca_a, cb_a, ca_b, cb_b;
+};
+
+// ---------------------------------------------------------------------------
+// k_pblock
+// ---------------------------------------------------------------------------
+// RHS mode: ACC = pointwise terms (all s) + sum_{s in block} D_{p_s} G_{n,s};
+//           G_{n,s} = F_s h_n + V_s' (h_{n+e_s} + n_s (m_s zeta_s gamma_s/beta) h_{n-e_s}).
+// PERTURB:  ACC = -sum_s dX/dq_s (beta p_s/2m_s) h_n + sum_{s in block} D_{p_s}(dX/dq_s h_n)
+//           (grad[s][qlin] = dX/dq_s): X^x W = sum_s dX/dq_s dW/dp_s in h, Eq. (Opticalexc).
+template <typename T, int NMAX, bool PERTURB>
+__global__ void __launch_bounds__(256)
+k_pblock(const Geom g, const Tabs tb, const PBlock pb, const T *__restrict__ X, T *__restrict__ out,
+         const double *__restrict__ grad) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *G = reinterpret_cast<T *>(smem_raw);
+  T *ACC = G + pb.tileP;
+  const int task = xcd_task(blockIdx.x, pb.nblk);
+  if (task >= pb.ntasks) return;
+  const int e = task % g.ne;
+  const int b0 = (task / g.ne) * pb.nb;
+  const int nbt = min(pb.nb, pb.nblocks - b0);
+  const int B = pb.B;
+  const int npts = nbt * B;
+  const long long E = g.E;
+  const long long off0 = (long long)e * E + (long long)b0 * B;
+  const int tid = threadIdx.x, bd = blockDim.x;
+  const int M = g.M;
+  const int NpM = g.Np[M - 1];
+  const int bpq = g.P / B;  // blocks per q point
+
+  // ---- ACC <- pointwise terms ---------------------------------------------
+  const long long rel0 = off0 - (long long)e * E;
+  if (PERTURB) {
+    // -sum_s dX/dq_s (beta p_s / 2 m_s) h_n
+    for (int j = tid; j < npts; j += bd) {
+      const int bl = j / B;
+      const int r = j - bl * B;
+      const int ob = b0 + bl;
+      const int ql = ob / bpq;
+      const int pix = (ob - ql * bpq) * B + r;
+      double c = 0.0;
+      for (int s = 0; s < M; ++s)
+        c += grad[(long long)s * g.Q + ql] * g.bm[s] * tb.pg[s * kTab + (pix / g.PS[s]) % g.Np[s]];
+      ACC[j + j / NpM] = -T(c) * X[off0 + j];
+    }
+  } else {
+    const T dmp = T(tb.damp[e]);
+    for (int j = tid; j < npts; j += bd) {
+      const int bl = j / B;
+      const int r = j - bl * B;
+      const int ob = b0 + bl;
+      const int ql = ob / bpq;
+      const int pix = (ob - ql * bpq) * B + r;
+      T acc = -dmp * X[off0 + j];
+      for (int s = 0; s < M; ++s) {
+        const int up = tb.up[e * 3 + s];
+        const int dn = tb.dn[e * 3 + s];
+        if (up < 0 && dn < 0) continue;
+        const double vpp = tb.Vp[s * kTab + (ql / g.QS[s]) % g.Nq[s]] *
+                           tb.pg[s * kTab + (pix / g.PS[s]) % g.Np[s]];
+        if (dn >= 0) acc += T(0.5 * tb.tc[e * 3 + s] * vpp) * X[(long long)dn * E + rel0 + j];
+        if (up >= 0) acc -= T(g.bm[s] * vpp) * X[(long long)up * E + rel0 + j];
+      }
+      ACC[j + j / NpM] = acc;
+    }
+  }
+
+  // ---- derivatives along the block axes --------------------------------------
+  for (int ax = 0; ax < pb.NB; ++ax) {
+    const int s = M - 1 - ax;  // p_M first, then p_{M-1}
+    const int Ns = g.Np[s];
+    if (PERTURB) {
+      for (int j = tid; j < npts; j += bd) {
+        const int ql = (b0 + j / B) / bpq;
+        G[j + j / NpM] = T(grad[(long long)s * g.Q + ql]) * X[off0 + j];
+      }
+    } else {
+      const int up = tb.up[e * 3 + s];
+      const int dn = tb.dn[e * 3 + s];
+      const double cc = tb.cc[e * 3 + s];
+      for (int j = tid; j < npts; j += bd) {
+        const int ql = (b0 + j / B) / bpq;
+        const double vp = tb.Vp[s * kTab + (ql / g.QS[s]) % g.Nq[s]];
+        T Gv = T(tb.F[(long long)s * g.Q + ql]) * X[off0 + j];
+        if (up >= 0) Gv += T(vp) * X[(long long)up * E + rel0 + j];
+        if (dn >= 0) Gv += T(vp * cc) * X[(long long)dn * E + rel0 + j];
+        G[j + j / NpM] = Gv;
+      }
+    }
+    __syncthreads();
+    const T ca = T(g.dp_ca[s]), cb = T(g.dp_cb[s]);
+    const int nlines = npts / Ns;
+    for (int l = tid; l < nlines; l += bd) {
+      int base, stride;
+      if (ax == 0) {  // rows of p_M, contiguous
+        base = l * (NpM + 1);
+        stride = 1;
+      } else {        // columns of p_{M-1}: stride one padded row
+        const int col = l % NpM;
+        const int blk = l / NpM;
+        base = blk * pb.rows * (NpM + 1) + col;
+        stride = NpM + 1;
+      }
+      T f[NMAX];
+#pragma unroll
+      for (int i = 0; i < NMAX; ++i) f[i] = (i < Ns) ? G[base + i * stride] : T(0);
+      compact_deriv<T, NMAX>(f, Ns, ca, cb);
+#pragma unroll
+      for (int i = 0; i < NMAX; ++i)
+        if (i < Ns) ACC[base + i * stride] += f[i];
+    }
+    __syncthreads();
+  }
+  for (int j = tid; j < npts; j += bd) out[off0 + j] = ACC[j + j / NpM];
+}
+
+// ---------------------------------------------------------------------------
+// k_qpass
+// ---------------------------------------------------------------------------
+enum Epi : int {
+  EPI_ACC = 0,  // Tacc += contribution
+  EPI_OUT = 1,  // xo = Tacc + contribution               (one RHS evaluation)
+  EPI_S1 = 2,   // k = Tacc + c;  yacc = X + dt/6 k;  xo = X + dt/2 k      (X is y)
+  EPI_S2 = 3,   // k;  yacc += dt/3 k;  xo = y + dt/2 k
+  EPI_S3 = 4,   // k;  yacc += dt/3 k;  xo = y + dt k
+  EPI_S4 = 5    // k;  xo (= y) = yacc + dt/6 k
+};
+
+// q-linear index and p index of a state position (within one element)
+__device__ __forceinline__ void split_pos(const Geom &g, const int rel, int &ql, int &pix) {
+  ql = rel / g.P;
+  pix = rel - ql * g.P;
+}
+
+// value of the field of mode s at relative position rel of element e
+template <typename T, int FIELD>
+__device__ __forceinline__ T field_at(const Geom &g, const Tabs &tb, const T *__restrict__ X,
+                                      const double *__restrict__ grad, const int e, const int s,
+                                      const int rel, const T w) {
+  if (FIELD == FQ) return w;
+  int ql, pix;
+  split_pos(g, rel, ql, pix);
+  if (FIELD == FX) return T(grad[(long long)s * g.Q + ql]) * w;
+  const int up = tb.up[e * 3 + s];
+  const int dn = tb.dn[e * 3 + s];
+  const double vp = tb.Vp[s * kTab + (ql / g.QS[s]) % g.Nq[s]];
+  T Gv = T(tb.F[(long long)s * g.Q + ql]) * w;
+  if (up >= 0) Gv += T(vp) * X[(long long)up * g.E + rel];
+  if (dn >= 0) Gv += T(vp * tb.cc[e * 3 + s]) * X[(long long)dn * g.E + rel];
+  return Gv;
+}
+
+template <typename T, int NMAX, bool TWO, int EPI, int FA, int FB>
+__global__ void __launch_bounds__(512)
+k_qpass(const Geom g, const Tabs tb, const QPass qp, const T *__restrict__ X, T *__restrict__ Tacc,
+        const T *__restrict__ y, T *__restrict__ yacc, T *__restrict__ xo, const double *__restrict__ grad,
+        const double dt) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *lds = reinterpret_cast<T *>(smem_raw);
+  const int task = xcd_task(blockIdx.x, qp.nblk);
+  if (task >= qp.ntasks) return;
+  const int chunk = task % qp.nchunk;
+  const int t2 = task / qp.nchunk;
+  const int rest = t2 % qp.nrest;
+  const int e = t2 / qp.nrest;
+  const int p0 = chunk * qp.pc;
+  const int pcn = min(qp.pc, qp.run - p0);
+  int rel = p0;
+  {
+    int r = rest;
+    const int r2 = r % qp.rN[2];
+    r /= qp.rN[2];
+    const int r1 = r % qp.rN[1];
+    const int r0 = r / qp.rN[1];
+    rel += r0 * qp.rS[0] + r1 * qp.rS[1] + r2 * qp.rS[2];
+  }
+  const int tid = threadIdx.x;
+  const int c = tid % qp.pc;
+  const int jb = tid / qp.pc;
+  const int Na = qp.Na;
+  const bool active = (c < pcn) && (jb < (TWO ? qp.Nb : 1));
+  const int lrel = rel + (TWO ? jb * qp.sb : 0) + c;  // line start within the element
+  const long long ebase = (long long)e * g.E;
+
+  T f[NMAX];
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i)
+    f[i] = (active && i < Na) ? X[ebase + lrel + i * qp.sa] : T(0);
+
+  if (TWO) {
+    const int Nb = qp.Nb, pc = qp.pc;
+    if (active) {
+#pragma unroll
+      for (int i = 0; i < NMAX; ++i)
+        if (i < Na) {
+          lds[(i * Nb + jb) * pc + c] =
+              field_at<T, FB>(g, tb, X, grad, e, qp.sb_mode, lrel + i * qp.sa, f[i]);
+        }
+    }
+    __syncthreads();
+    const int ja = tid / pc;
+    if (c < pcn && ja < Na) {
+      T h[NMAX];
+#pragma unroll
+      for (int i = 0; i < NMAX; ++i) h[i] = (i < Nb) ? lds[(ja * Nb + i) * pc + c] : T(0);
+      compact_deriv<T, NMAX>(h, Nb, T(qp.ca_b), T(qp.cb_b));
+#pragma unroll
+      for (int i = 0; i < NMAX; ++i)
+        if (i < Nb) lds[(ja * Nb + i) * pc + c] = h[i];
+    }
+    __syncthreads();
+  }
+  if (!active) return;  // no barrier below this point
+
+  // field along a (a q axis: W itself; p axis: built from W and neighbours)
+  T d[NMAX];
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i) {
+    if (FA == FQ)
+      d[i] = f[i];
+    else
+      d[i] = (i < Na) ? field_at<T, FA>(g, tb, X, grad, e, qp.sa_mode, lrel + i * qp.sa, f[i]) : T(0);
+  }
+  compact_deriv<T, NMAX>(d, Na, T(qp.ca_a), T(qp.cb_a));
+
+  // coefficients: -p_s/m_s for q-type axes (p_s is fixed along the line)
+  int ql0, pix0;
+  split_pos(g, lrel, ql0, pix0);
+  T ka = T(1), kb = T(1);
+  if (FA == FQ) {
+    const int s = qp.sa_mode;
+    ka = T(-tb.pm[s * kTab + (pix0 / g.PS[s]) % g.Np[s]]);
+  }
+  if (TWO && FB == FQ) {
+    const int s = qp.sb_mode;
+    kb = T(-tb.pm[s * kTab + (pix0 / g.PS[s]) % g.Np[s]]);
+  }
+  const T h6 = T(dt / 6.0), h3 = T(dt / 3.0), h2 = T(dt / 2.0), h1 = T(dt);
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i) {
+    if (i < Na) {
+      T kv = ka * d[i];
+      if (TWO) kv += kb * lds[(i * qp.Nb + jb) * qp.pc + c];
+      const long long idx = ebase + lrel + i * qp.sa;
+      if (EPI == EPI_ACC) {
+        Tacc[idx] += kv;
+      } else {
+        kv += Tacc[idx];
+        if (EPI == EPI_OUT) {
+          xo[idx] = kv;
+        } else if (EPI == EPI_S1) {
+          yacc[idx] = f[i] + h6 * kv;
+          xo[idx] = f[i] + h2 * kv;
+        } else if (EPI == EPI_S2) {
+          const T yv = y[idx];
+          yacc[idx] += h3 * kv;
+          xo[idx] = yv + h2 * kv;
+        } else if (EPI == EPI_S3) {
+          const T yv = y[idx];
+          yacc[idx] += h3 * kv;
+          xo[idx] = yv + h1 * kv;
+        } else {  // EPI_S4
+          xo[idx] = yacc[idx] + h6 * kv;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// reductions and small kernels (FP64)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// partial[block] = sum over this block's share of element 0 of
+// Cw[qlin] * wp[pidx] * W[qlin * P + pidx]   (fixed order for a fixed grid)
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_reduce_w0(const T *__restrict__ W, const double *__restrict__ Cw, const double *__restrict__ wp,
+            const int Q, const int P, double *__restrict__ partial) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  const int n = Q * P;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const int ql = i / P;
+    const int pi = i - ql * P;
+    s += Cw[ql] * wp[pi] * double(W[i]);
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// out[0] = scale * sum(partial[0..n)), summed in a fixed order by one block.
+__global__ void __launch_bounds__(256)
+k_reduce_final(const double *__restrict__ partial, const int n, const double scale,
+               double *__restrict__ out) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += partial[i];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[0] = scale * ((sh[0] + sh[1]) + (sh[2] + sh[3]));
+}
+
+// element 0: h_0 = exp(-beta H / 2) = sq[qlin] * sp[pidx] (unnormalised); other elements: 0
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_boltzmann(T *__restrict__ W, const double *__restrict__ sq, const double *__restrict__ sp,
+            const int Q, const int P, const long long total) {
+  const int n0 = Q * P;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < total;
+       i += (long long)gridDim.x * 256) {
+    if (i < n0) {
+      const int ii = (int)i;
+      const int ql = ii / P;
+      const int pi = ii - ql * P;
+      W[i] = T(sq[ql] * sp[pi]);
+    } else {
+      W[i] = T(0);
+    }
+  }
+}
+
+// W <- W * sq[qlin] * sp[pidx] (mul != 0) or W / (sq * sp) (mul == 0), every element
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_sym_scale(T *__restrict__ W, const double *__restrict__ sq, const double *__restrict__ sp,
+            const int Q, const int P, const long long total, const int mul) {
+  const long long E = (long long)Q * P;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < total;
+       i += (long long)gridDim.x * 256) {
+    const int ii = (int)(i % E);
+    const int ql = ii / P;
+    const int pi = ii - ql * P;
+    const double f = sq[ql] * sp[pi];
+    W[i] = mul ? T(double(W[i]) * f) : T(double(W[i]) / f);
+  }
+}
+
+// W[0 .. n0) *= 1 / (dV * sum), sum read from device memory
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_normalise(T *__restrict__ W, const double *__restrict__ sum, const double dV, const int n0) {
+  const double inv = 1.0 / (dV * sum[0]);
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n0; i += gridDim.x * 256)
+    W[i] = T(double(W[i]) * inv);
+}
+
+// flag[0] = 1 if any value is not finite
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_check_finite(const T *__restrict__ W, const long long n, int *__restrict__ flag) {
+  int bad = 0;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (long long)gridDim.x * 256) {
+    const double v = double(W[i]);
+    bad |= !(v - v == 0.0);
+  }
+  if (bad) flag[0] = 1;  // benign race: every writer stores 1
+}
+
+// dst = src, 16-byte vectors
+__global__ void __launch_bounds__(256)
+k_stream_copy(uint4 *__restrict__ dst, const uint4 *__restrict__ src, const long long n16) {
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n16;
+       i += (long long)gridDim.x * 256)
+    dst[i] = src[i];
+}
+
+}  // namespace chfpe

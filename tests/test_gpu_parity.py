@@ -1,0 +1,183 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Bar (FP64 path): relative L2 error <= 1e-10 on states, responses and
+observables; one right-hand side and a few RK4 steps agree to ~1e-14.
+Sizes: small grids that span several tiles with ragged tails, the one-mode
+workload at full size, and the two-mode 32^4 workload at full size in the
+launch configuration the benchmark times (sampled t1/t2 entries).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as orc
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import torch
+    import paper_2509_25840_amd as pk
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return pk
+
+
+def solver(pk, w):
+    return pk.Solver(pk.params_from_workload(w))
+
+
+def phys_state(w, seed, noise=0.05):
+    """A seeded state with the physical shape: the Boltzmann envelope of the
+    model (from the oracle) on every element, times 1 + smooth + noise."""
+    env = orc.boltzmann(w)[0]
+    sm = wl.smooth_state(w, seed=seed)
+    sm = sm / np.abs(sm).max()
+    nz = wl.noise_state(w, seed=seed + 1000)
+    return env[None] * (1.0 + 0.3 * sm + noise * nz)
+
+
+SMALL = {
+    "m1_n12_k3": wl.workload("one_mode_48", Nq=[12], Np=[13], K=3),
+    "m2_n10_k2": wl.workload("two_mode_32", Nq=[10, 9], Np=[11, 10], K=2),
+    "m2_n12_k3": wl.workload("two_mode_32", Nq=[12, 12], Np=[12, 12], K=3),
+    "m3_n8_k2": wl.workload("three_mode_24", Nq=[8, 7, 8], Np=[8, 9, 7], K=2),
+    "m3_n6_k3": wl.workload("three_mode_24", Nq=[6, 6, 6], Np=[6, 6, 6], K=3),
+}
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_rhs_parity_small(pk, name):
+    w = SMALL[name]
+    say(f"[rhs] {name} shape={orc.state_shape(w)}")
+    W = phys_state(w, seed=1)
+    ref = orc.rhs(w, W)
+    with solver(pk, w) as s:
+        s.set_state(W)
+        s.rhs()
+        got = s.get_state().reshape(W.shape)
+    assert rel_l2(got, ref) < 1e-13
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_rk4_parity_small(pk, name):
+    w = SMALL[name]
+    say(f"[rk4] {name}")
+    W = phys_state(w, seed=3)
+    ref = orc.rk4(w, W, 3, 0.002)
+    with solver(pk, w) as s:
+        s.set_state(W)
+        s.propagate(3, 0.002)
+        got = s.get_state().reshape(W.shape)
+    assert rel_l2(got, ref) < 1e-13
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_perturb_and_observe_parity_small(pk, name):
+    w = SMALL[name]
+    M = w["M"]
+    say(f"[perturb] {name}")
+    X = wl.optical(M, lin=[1.0, -0.7, 0.4][:M],
+                   quad=[[0.2, 0.05, -0.03], [0.05, -0.1, 0.02], [-0.03, 0.02, 0.3]][:M])
+    X["quad"] = [row[:M] for row in X["quad"]]
+    W = phys_state(w, seed=4)
+    ref = orc.perturb(w, X, W)
+    with solver(pk, w) as s:
+        s.set_state(W)
+        v_gpu = s.observe(X)
+        s.perturb(X)
+        got = s.get_state().reshape(W.shape)
+    assert rel_l2(got, ref) < 1e-13
+    v_ref = orc.observe(w, X, W)
+    assert abs(v_gpu - v_ref) <= 1e-13 * max(abs(v_ref), 1e-300)
+
+
+@pytest.mark.parametrize("name", ["m1_n12_k3", "m2_n10_k2", "m3_n8_k2"])
+def test_equilibrate_parity_small(pk, name):
+    w = SMALL[name]
+    say(f"[equilibrate] {name}")
+    ref = orc.equilibrate(w, 40, 0.004)
+    with solver(pk, w) as s:
+        s.equilibrate(40, 0.004)
+        got = s.get_state().reshape(ref.shape)
+    assert rel_l2(got, ref) < 1e-12
+
+
+def test_response_1d_parity_one_mode_full(pk):
+    """The one-mode 48 x 48, depth-3 workload: equilibration and 1D response
+    (shortened to 600 + 800 steps so that the oracle stays fast)."""
+    w = wl.workload("one_mode_48")
+    say("[response_1d] one_mode_48")
+    Weq = orc.equilibrate(w, 600, w["dt"])
+    ref = orc.response_1d(w, w["A"], Weq, 800, 1, w["dt"])
+    with solver(pk, w) as s:
+        s.equilibrate(600, w["dt"])
+        assert rel_l2(s.get_state(), Weq) < 1e-11
+        got = s.response_1d(w["A"], 800, 1, w["dt"])
+    assert rel_l2(got, ref) < FP64_TOL
+
+
+@pytest.mark.parametrize("name", ["m2_n10_k2", "m3_n8_k2", "m3_n6_k3"])
+def test_response_2d_parity_small(pk, name):
+    w = SMALL[name]
+    M = w["M"]
+    A = wl.workload("three_mode_24")["A"]
+    B = wl.workload("three_mode_24")["B"]
+    A = {"lin": A["lin"][:M], "quad": [r[:M] for r in A["quad"][:M]]}
+    B = {"lin": B["lin"][:M], "quad": [r[:M] for r in B["quad"][:M]]}
+    say(f"[response_2d] {name}")
+    Weq = orc.equilibrate(w, 10, 0.004)
+    ref = orc.response_2d(w, A, B, A, Weq, 5, 6, 2, 3, 0.004)
+    with solver(pk, w) as s:
+        s.equilibrate(10, 0.004)
+        got = s.response_2d(A, B, A, 5, 6, 2, 3, 0.004)
+    assert rel_l2(got, ref) < FP64_TOL
+
+
+def test_two_mode_full_size_rhs_and_steps(pk):
+    """Two modes, 32^4, depth 3 (10 elements): one right-hand side and two RK4
+    steps on a seeded smooth state."""
+    w = wl.workload("two_mode_32")
+    say("[full] two_mode_32 rhs + 2 steps")
+    W = phys_state(w, seed=5, noise=0.0)
+    ref_rhs = orc.rhs(w, W)
+    ref_2 = orc.rk4(w, W, 2, w["dt"])
+    with solver(pk, w) as s:
+        s.set_state(W)
+        s.rhs()
+        assert rel_l2(s.get_state(), ref_rhs) < 1e-13
+        s.set_state(W)
+        s.propagate(2, w["dt"])
+        assert rel_l2(s.get_state(), ref_2) < 1e-13
+
+
+def test_two_mode_full_size_response_2d_sampled(pk):
+    """The benchmarked 2D THz-Raman run (64 t1 x 256 t2, stride 1) on the GPU;
+    sampled t1 columns (0, 1, 3) and the first 4 t2 rows against the oracle,
+    both starting from the same equilibrium (the discrete Boltzmann state)."""
+    w = wl.workload("two_mode_32")
+    say("[full] two_mode_32 response_2d 64x256 sampled")
+    Wb = orc.boltzmann(w)
+    cols = [0, 1, 3]
+    ref = orc.response_2d(w, w["A"], w["B"], w["C"], Wb, 64, 4, 1, 1, w["dt"], j1_list=cols)
+    with solver(pk, w) as s:
+        s.set_state(Wb)
+        s.use_state_as_equilibrium()
+        got = s.response_2d(w["A"], w["B"], w["C"], 64, 256, 1, 1, w["dt"])
+    assert np.all(np.isfinite(got))
+    assert rel_l2(got[:4, cols], ref[:4, cols]) < FP64_TOL
