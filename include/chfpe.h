@@ -167,6 +167,20 @@ int chfpe_perturb(chfpe_ctx *ctx, const chfpe_optical *X);
  * midpoint rule as for Z above). */
 int chfpe_observe(chfpe_ctx *ctx, const chfpe_optical *X, double *value);
 
+/* Spectra of Eqs. (1DIR_Raman) and (2DThz_Raman) as discrete Fourier sums
+ * on the device (rectangle rule, weight 1 at t = 0, no window or padding),
+ * with omega_k = 2 pi k / (n tau):
+ *   1D: I[k] = omega_k Im{ sum_j tau exp(+i omega_k t_j) R[j] },  t_j = j tau;
+ *       omega (optional, may be NULL) receives omega_k.
+ *   2D: I[k2 * n_t1 + k1] = Im{ tau1 tau2 sum_{j1,j2}
+ *           exp(-i omega1_k1 t1_j1 - i omega2_k2 t2_j2) R[j2 * n_t1 + j1] }.
+ * R, omega and I are host arrays; device scratch is allocated and freed per
+ * call; the call synchronizes hip_stream (NULL: null stream). */
+int chfpe_spectrum_1d(const double *R, int64_t n, double tau, double *omega, double *I,
+                      void *hip_stream);
+int chfpe_spectrum_2d(const double *R, int64_t n_t1, int64_t n_t2, double tau1, double tau2,
+                      double *I, void *hip_stream);
+
 /* Bandwidth reference: copy `bytes` bytes (a multiple of 16) from src to
  * dst, both device pointers, with a plain streaming kernel on hip_stream. */
 int chfpe_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream);

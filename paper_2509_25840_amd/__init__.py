@@ -15,7 +15,8 @@ import os
 import numpy as np
 
 __all__ = ["Params", "Optical", "Solver", "ChfpeError", "lib", "params_from_workload",
-           "optical_from_dict", "workspace_bytes", "stream_copy", "LIB_PATH"]
+           "optical_from_dict", "workspace_bytes", "stream_copy", "spectrum_1d", "spectrum_2d",
+           "LIB_PATH"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libchfpe.so")
@@ -95,6 +96,10 @@ def lib():
     L.chfpe_perturb.restype = ctypes.c_int
     L.chfpe_observe.argtypes = [vp, O, dp]
     L.chfpe_observe.restype = ctypes.c_int
+    L.chfpe_spectrum_1d.argtypes = [dp, i64, ctypes.c_double, dp, dp, vp]
+    L.chfpe_spectrum_1d.restype = ctypes.c_int
+    L.chfpe_spectrum_2d.argtypes = [dp, i64, i64, ctypes.c_double, ctypes.c_double, dp, vp]
+    L.chfpe_spectrum_2d.restype = ctypes.c_int
     L.chfpe_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
     L.chfpe_stream_copy.restype = ctypes.c_int
     L.chfpe_set_kernel_timing.argtypes = [vp, i32]
@@ -160,6 +165,34 @@ def _dptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def spectrum_1d(R, tau: float, stream=None):
+    """(omega, I) of Eq. (1DIR_Raman) computed on the device."""
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    om = np.empty(R.size)
+    I = np.empty(R.size)
+    rc = lib().chfpe_spectrum_1d(_dptr(R), R.size, float(tau), _dptr(om), _dptr(I), _stream_handle(stream))
+    if rc != 0:
+        raise ChfpeError(rc, "spectrum_1d failed")
+    return om, I
+
+
+def spectrum_2d(R, tau1: float, tau2: float, stream=None):
+    """I(omega1, omega2) of Eq. (2DThz_Raman) on the device; R has shape (n_t2, n_t1)."""
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    n2, n1 = R.shape
+    I = np.empty_like(R)
+    rc = lib().chfpe_spectrum_2d(_dptr(R), n1, n2, float(tau1), float(tau2), _dptr(I), _stream_handle(stream))
+    if rc != 0:
+        raise ChfpeError(rc, "spectrum_2d failed")
+    return I
+
+
 class Solver:
     """One solver context: workspace allocated by torch on ``device``,
     work issued on the current torch stream of that device."""
@@ -186,7 +219,22 @@ class Solver:
         if rc != 0:
             raise ChfpeError(rc, L.chfpe_last_error(None).decode())
         self.params = params
+        self._ws_ptr = aligned
+        self._ws_bytes = nbytes
         self.count = int(L.chfpe_state_count(self._ctx))
+
+    def rebuild(self):
+        """Run chfpe_setup again into the same workspace (tables rebuilt and
+        uploaded; the equilibrium is dropped)."""
+        L = lib()
+        L.chfpe_destroy(self._ctx)
+        self._ctx = ctypes.c_void_p()
+        rc = L.chfpe_setup(ctypes.byref(self.params), ctypes.c_void_p(self._ws_ptr),
+                           ctypes.c_size_t(self._ws_bytes), ctypes.c_void_p(self.stream.cuda_stream),
+                           ctypes.byref(self._ctx))
+        if rc != 0:
+            self._ctx = None
+            raise ChfpeError(rc, L.chfpe_last_error(None).decode())
 
     # -- helpers ---------------------------------------------------------------
     def _check(self, rc: int):

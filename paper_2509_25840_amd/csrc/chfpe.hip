@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <string>
@@ -29,7 +30,8 @@ namespace {
 
 thread_local std::string g_setup_error = "no error";
 
-constexpr int kPBlockThreads = 256;  // k_pblock workgroup size
+constexpr int kPBlockThreads = 256;  // k_pblock workgroup size (upper bound)
+constexpr int kPBlockRPT = 16;       // rows per k_pblock thread
 constexpr int kQThreadsMax = 512;    // largest k_qpass workgroup
 
 constexpr int kNumKinds = 9;
@@ -225,6 +227,8 @@ struct chfpe_ctx {
   double *rbuf = nullptr;
   size_t rbuf_cap = 0;
   std::string err = "no error";
+  int tune_pb_nb = 0;   // blocks per k_pblock task (0: automatic)
+  int tune_q_pc = 0;    // run positions per two-axis k_qpass tile (0: automatic)
   // kernel timing
   int timing_every = 0;
   long long step_counter = 0;
@@ -442,8 +446,9 @@ void plan_two(chfpe_ctx *c, int a, int b, int run, std::vector<int> rest, QPass 
               size_t &lds, int &nmax) {
   const Derived &d = c->d;
   const int Na = axis_len(d, a), Nb = axis_len(d, b);
-  int pc = 16;
-  while (pc > 1 && ((size_t)Na * Nb * pc * sizeof(double) > 80 * 1024 || std::max(Na, Nb) * pc > kQThreadsMax))
+  int pc = c->tune_q_pc > 0 ? c->tune_q_pc : 16;
+  const size_t lds_cap = c->tune_q_pc > 0 ? 160 * 1024 : 80 * 1024;
+  while (pc > 1 && ((size_t)Na * Nb * pc * sizeof(double) > lds_cap || std::max(Na, Nb) * pc > kQThreadsMax))
     pc /= 2;
   out = make_qpass(c, a, b, run, rest, pc);
   thr = (std::max(Na, Nb) * out.pc + 63) / 64 * 64;
@@ -466,20 +471,27 @@ void plan(chfpe_ctx *c) {
   // k_pblock: the innermost one (one mode) or two p axes
   PBlock &pb = ln.pb;
   pb.NB = M == 1 ? 1 : 2;
-  pb.B = M == 1 ? d.Np[0] : d.Np[M - 2] * d.Np[M - 1];
-  pb.rows = pb.B / NpM;
+  pb.cols = NpM;
+  pb.rows = M == 1 ? 1 : d.Np[M - 2];
+  pb.B = pb.rows * pb.cols;
   pb.nblocks = (int)(d.E / pb.B);
-  const size_t blk_bytes = 2 * (size_t)pb.rows * (NpM + 1) * sizeof(double);  // G + ACC
-  int nb = std::max<int>(1, (int)((40 * 1024) / blk_bytes));
-  while (nb > 1 && (long long)nb * pb.B > 4096) --nb;
+  pb.bpq = d.P / pb.B;
+  pb.RG = std::max(1, kPBlockThreads / pb.cols);
+  // lines per task ~ threads; rows per thread <= kPBlockRPT; LDS <= ~80 KB
+  const size_t blk_bytes = (size_t)pb.NB * pb.rows * (NpM + 1) * sizeof(double);
+  const int lines_per_blk = pb.rows + (pb.NB == 2 ? pb.cols : 0);
+  int nb = std::max(1, (pb.RG * pb.cols) / lines_per_blk);
+  if (c->tune_pb_nb > 0) nb = c->tune_pb_nb;
+  while (nb > 1 && ((long long)nb * pb.rows > (long long)kPBlockRPT * pb.RG || nb * blk_bytes > 80 * 1024))
+    --nb;
   nb = std::min(nb, pb.nblocks);
   pb.nb = nb;
   pb.tileP = nb * pb.rows * (NpM + 1);
   pb.ntasks = d.ne * ((pb.nblocks + nb - 1) / nb);
   pb.nblk = pad8(pb.ntasks);
   ln.pb_lds = (size_t)nb * blk_bytes;
-  ln.pb_threads = kPBlockThreads;
-  ln.pb_nmax = nmax_bucket(M == 1 ? d.Np[0] : std::max(d.Np[M - 2], d.Np[M - 1]));
+  ln.pb_threads = pb.RG * pb.cols;
+  ln.pb_nmax = nmax_bucket(std::max(pb.rows, pb.cols));
   // strided-axis passes
   if (M == 1) {
     ln.has_qa = false;
@@ -568,7 +580,7 @@ void allow_lds(K kern, size_t bytes) {
 template <int NMAX, bool PERTURB>
 void launch_pblock_n(chfpe_ctx *c, const double *X, double *out, const double *grad) {
   const Launch &ln = c->ln;
-  auto kern = k_pblock<double, NMAX, PERTURB>;
+  auto kern = k_pblock<double, NMAX, kPBlockRPT, PERTURB>;
   allow_lds(kern, ln.pb_lds);
   hipLaunchKernelGGL(kern, dim3(ln.pb.nblk), dim3(ln.pb_threads), ln.pb_lds, c->stream, c->g, c->tb, ln.pb,
                      X, out, grad);
@@ -818,6 +830,8 @@ int chfpe_setup(const chfpe_params *p, void *dev_workspace, size_t ws_bytes, voi
   for (int i = 0; i < 7; ++i) *bp[i] = (double *)at(L.bufs[i]);
 
   make_geom(c);
+  if (const char *v = std::getenv("CHFPE_TUNE_PB_NB")) c->tune_pb_nb = std::atoi(v);
+  if (const char *v = std::getenv("CHFPE_TUNE_Q_PC")) c->tune_q_pc = std::atoi(v);
   std::vector<double> F, Vp, pm, pg, sq, sp, wp, cc, tc, damp;
   std::vector<int> up, dn;
   build_tables(c, F, Vp, pm, pg, sq, sp, wp, up, dn, cc, tc, damp);
@@ -1049,6 +1063,67 @@ int chfpe_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream
   hipLaunchKernelGGL(k_stream_copy, dim3(4096), dim3(256), 0, reinterpret_cast<hipStream_t>(hip_stream),
                      reinterpret_cast<uint4 *>(dst), reinterpret_cast<const uint4 *>(src), n16);
   return hipGetLastError() == hipSuccess ? CHFPE_OK : CHFPE_EDEVICE;
+}
+
+namespace {
+struct DevBuf {
+  void *p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+}  // namespace
+
+int chfpe_spectrum_1d(const double *R, int64_t n, double tau, double *omega, double *I, void *hip_stream) {
+  if (!R || !I || n < 1 || n > (1LL << 24) || !(tau > 0) || !std::isfinite(tau)) return CHFPE_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  DevBuf bR, bz, bo, bI;
+  if (hipMalloc(&bR.p, n * sizeof(double)) != hipSuccess || hipMalloc(&bz.p, n * sizeof(double2)) != hipSuccess ||
+      hipMalloc(&bo.p, n * sizeof(double2)) != hipSuccess || hipMalloc(&bI.p, n * sizeof(double)) != hipSuccess)
+    return CHFPE_ENOMEM;
+  if (hipMemcpyAsync(bR.p, R, n * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess) return CHFPE_EDEVICE;
+  const int nb = (int)((n + 255) / 256);
+  hipLaunchKernelGGL(k_to_complex, dim3(nb), dim3(256), 0, st, (const double *)bR.p, (double2 *)bz.p, n);
+  // sum_j exp(+i omega_k t_j) R_j, omega_k = 2 pi k / (n tau)
+  hipLaunchKernelGGL(k_dft_rows, dim3(nb), dim3(256), 0, st, (const double2 *)bz.p, (double2 *)bo.p, 1, (int)n,
+                     (int)n, 1, (int)n, 1, 1.0);
+  const double dw = 2.0 * M_PI / ((double)n * tau);
+  hipLaunchKernelGGL(k_spectrum_out, dim3(nb), dim3(256), 0, st, (const double2 *)bo.p, (long long)n, (int)n,
+                     tau, dw, 1, (double *)bI.p);
+  if (hipMemcpyAsync(I, bI.p, n * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess) return CHFPE_EDEVICE;
+  if (hipStreamSynchronize(st) != hipSuccess) return CHFPE_EDEVICE;
+  if (hipGetLastError() != hipSuccess) return CHFPE_EDEVICE;
+  if (omega)
+    for (int64_t k = 0; k < n; ++k) omega[k] = dw * (double)k;
+  return CHFPE_OK;
+}
+
+int chfpe_spectrum_2d(const double *R, int64_t n_t1, int64_t n_t2, double tau1, double tau2, double *I,
+                      void *hip_stream) {
+  if (!R || !I || n_t1 < 1 || n_t2 < 1 || n_t1 * n_t2 > (1LL << 26) || !(tau1 > 0) || !(tau2 > 0) ||
+      !std::isfinite(tau1) || !std::isfinite(tau2))
+    return CHFPE_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  const long long n = n_t1 * n_t2;
+  DevBuf bR, bz, bo, bI;
+  if (hipMalloc(&bR.p, n * sizeof(double)) != hipSuccess || hipMalloc(&bz.p, n * sizeof(double2)) != hipSuccess ||
+      hipMalloc(&bo.p, n * sizeof(double2)) != hipSuccess || hipMalloc(&bI.p, n * sizeof(double)) != hipSuccess)
+    return CHFPE_ENOMEM;
+  if (hipMemcpyAsync(bR.p, R, n * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess) return CHFPE_EDEVICE;
+  const int nb = (int)((n + 255) / 256);
+  hipLaunchKernelGGL(k_to_complex, dim3(nb), dim3(256), 0, st, (const double *)bR.p, (double2 *)bz.p, n);
+  // along t1 (rows of length n_t1), exp(-i omega1 t1)
+  hipLaunchKernelGGL(k_dft_rows, dim3(nb), dim3(256), 0, st, (const double2 *)bz.p, (double2 *)bo.p, (int)n_t2,
+                     (int)n_t1, (int)n_t1, 1, (int)n_t1, 1, -1.0);
+  // along t2 (columns, stride n_t1), exp(-i omega2 t2)
+  hipLaunchKernelGGL(k_dft_rows, dim3(nb), dim3(256), 0, st, (const double2 *)bo.p, (double2 *)bz.p, (int)n_t1,
+                     (int)n_t2, 1, (int)n_t1, 1, (int)n_t1, -1.0);
+  hipLaunchKernelGGL(k_spectrum_out, dim3(nb), dim3(256), 0, st, (const double2 *)bz.p, n, (int)n_t1, tau1 * tau2,
+                     0.0, 0, (double *)bI.p);
+  if (hipMemcpyAsync(I, bI.p, n * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess) return CHFPE_EDEVICE;
+  if (hipStreamSynchronize(st) != hipSuccess) return CHFPE_EDEVICE;
+  if (hipGetLastError() != hipSuccess) return CHFPE_EDEVICE;
+  return CHFPE_OK;
 }
 
 int chfpe_set_kernel_timing(chfpe_ctx *c, int32_t every) {

@@ -140,16 +140,21 @@ __device__ __forceinline__ int xcd_task(const int bid, const int nblk) {
 // Tile descriptions passed by value.
 // ---------------------------------------------------------------------------
 // k_pblock: the innermost NB p axes (NB = 1 for one mode, else 2) form a
-// contiguous block of B values; a task is one element and a run of nb
-// consecutive blocks.  G (the field being differentiated) and ACC (the
-// partial right-hand side) live in LDS with one pad value per p_M row.
+// contiguous block of rows x cols values (cols = Np_M; rows = Np_{M-1}, or 1
+// for one mode); a task is one element and a run of nb consecutive blocks.
+// Thread t owns column t % cols of every RG-th row of the run, so global
+// accesses are row-contiguous and coordinates need no division per point.
+// LDS holds the fields of the row axis (p_M) and column axis (p_{M-1}) with
+// one pad value per row.
 struct PBlock {
-  int NB;            // p axes inside a block
-  int B;             // values per block
-  int rows;          // B / Np[M-1]
+  int NB;            // p axes inside a block (1 or 2)
+  int rows, cols;    // block shape
+  int B;             // rows * cols
   int nb;            // blocks per task
-  int nblocks;       // blocks per element (E / B)
-  int tileP;         // padded values of one LDS array
+  int nblocks;       // blocks per element
+  int bpq;           // blocks per q point (P / B)
+  int RG;            // row groups; threads = cols * RG
+  int tileP;         // padded values of one LDS field = nb * rows * (cols + 1)
   int ntasks, nblk;
 };
 
@@ -182,115 +187,148 @@ struct QPass {
 // ---------------------------------------------------------------------------
 // k_pblock
 // ---------------------------------------------------------------------------
-// RHS mode: ACC = pointwise terms (all s) + sum_{s in block} D_{p_s} G_{n,s};
-//           G_{n,s} = F_s h_n + V_s' (h_{n+e_s} + n_s (m_s zeta_s gamma_s/beta) h_{n-e_s}).
-// PERTURB:  ACC = -sum_s dX/dq_s (beta p_s/2m_s) h_n + sum_{s in block} D_{p_s}(dX/dq_s h_n)
-//           (grad[s][qlin] = dX/dq_s): X^x W = sum_s dX/dq_s dW/dp_s in h, Eq. (Opticalexc).
-template <typename T, int NMAX, bool PERTURB>
+// RHS mode: out = pointwise terms (all s) + sum_{s in block} D_{p_s} G_{n,s},
+//   G_{n,s} = F_s h_n + V_s' (h_{n+e_s} + n_s (m_s zeta_s gamma_s/beta) h_{n-e_s}),
+//   pointwise = sum_s V_s' p_s [ (n_s zeta_s gamma_s/2) h_{n-e_s} - (beta/2m_s) h_{n+e_s} ]
+//               - sum_s n_s gamma_s h_n.
+// PERTURB: out = -sum_s dX/dq_s (beta p_s/2m_s) h_n + sum_{s in block} D_{p_s}(dX/dq_s h_n)
+//   (grad[s][qlin] = dX/dq_s): X^x W = sum_s dX/dq_s dW/dp_s written for h, Eq. (Opticalexc).
+// Three phases: (1) one pass over the run loads h_n and its neighbours once,
+// keeps the pointwise terms in registers and writes both derivative fields to
+// LDS; (2) row and column lines are solved together; (3) one pass writes out.
+template <typename T, int NMAX, int RPT, bool PERTURB>
 __global__ void __launch_bounds__(256)
 k_pblock(const Geom g, const Tabs tb, const PBlock pb, const T *__restrict__ X, T *__restrict__ out,
          const double *__restrict__ grad) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *G = reinterpret_cast<T *>(smem_raw);
-  T *ACC = G + pb.tileP;
+  T *Ga = reinterpret_cast<T *>(smem_raw);  // row axis p_M
+  T *Gb = Ga + pb.tileP;                    // column axis p_{M-1} (NB == 2)
   const int task = xcd_task(blockIdx.x, pb.nblk);
   if (task >= pb.ntasks) return;
   const int e = task % g.ne;
   const int b0 = (task / g.ne) * pb.nb;
   const int nbt = min(pb.nb, pb.nblocks - b0);
-  const int B = pb.B;
-  const int npts = nbt * B;
-  const long long E = g.E;
-  const long long off0 = (long long)e * E + (long long)b0 * B;
-  const int tid = threadIdx.x, bd = blockDim.x;
   const int M = g.M;
-  const int NpM = g.Np[M - 1];
-  const int bpq = g.P / B;  // blocks per q point
+  const int rows = pb.rows, cols = pb.cols, cp = pb.cols + 1;
+  const int nrows = nbt * rows;
+  const long long E = g.E;
+  const long long eoff = (long long)e * E;
+  const int tid = threadIdx.x;
+  const int col = tid % cols;
+  const int rg = tid / cols;
+  const bool owner = rg < pb.RG;
+  const int sa = M - 1;               // row axis
+  const int sb = M - 2;               // column axis (NB == 2)
+  const int so = M - 3;               // outer p axis inside the p-block (three modes)
 
-  // ---- ACC <- pointwise terms ---------------------------------------------
-  const long long rel0 = off0 - (long long)e * E;
-  if (PERTURB) {
-    // -sum_s dX/dq_s (beta p_s / 2 m_s) h_n
-    for (int j = tid; j < npts; j += bd) {
-      const int bl = j / B;
-      const int r = j - bl * B;
-      const int ob = b0 + bl;
-      const int ql = ob / bpq;
-      const int pix = (ob - ql * bpq) * B + r;
+  int up[3], dn[3];
+  double cc[3], tc[3];
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    up[s] = (!PERTURB && s < M) ? tb.up[e * 3 + s] : -1;
+    dn[s] = (!PERTURB && s < M) ? tb.dn[e * 3 + s] : -1;
+    cc[s] = (!PERTURB && s < M) ? tb.cc[e * 3 + s] : 0.0;
+    tc[s] = (!PERTURB && s < M) ? tb.tc[e * 3 + s] : 0.0;
+  }
+  const T dmp = PERTURB ? T(0) : T(tb.damp[e]);
+  const double p_col = tb.pg[sa * kTab + col];
+
+  // ---- phase 1 ----------------------------------------------------------------
+  T pw[RPT];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    pw[k] = T(0);
+    const int R = rg + k * pb.RG;
+    if (!owner || R >= nrows) continue;
+    const int blk = R / rows;
+    const int r = R - blk * rows;
+    const int ob = b0 + blk;
+    const int ql = ob / pb.bpq;
+    const int jo = ob - ql * pb.bpq;       // outer p index inside the p-block
+    const int rel = ob * pb.B + r * cols + col;
+    const int li = R * cp + col;
+    const T h = X[eoff + rel];
+    // p coordinates of this point on every axis
+    double ps[3];
+    ps[sa] = p_col;
+    if (pb.NB == 2) ps[sb] = tb.pg[sb * kTab + r];
+    if (M == 3) ps[so] = tb.pg[so * kTab + jo];
+    if (PERTURB) {
       double c = 0.0;
-      for (int s = 0; s < M; ++s)
-        c += grad[(long long)s * g.Q + ql] * g.bm[s] * tb.pg[s * kTab + (pix / g.PS[s]) % g.Np[s]];
-      ACC[j + j / NpM] = -T(c) * X[off0 + j];
-    }
-  } else {
-    const T dmp = T(tb.damp[e]);
-    for (int j = tid; j < npts; j += bd) {
-      const int bl = j / B;
-      const int r = j - bl * B;
-      const int ob = b0 + bl;
-      const int ql = ob / bpq;
-      const int pix = (ob - ql * bpq) * B + r;
-      T acc = -dmp * X[off0 + j];
+      for (int s = 0; s < M; ++s) c += grad[(long long)s * g.Q + ql] * g.bm[s] * ps[s];
+      pw[k] = -T(c) * h;
+      Ga[li] = T(grad[(long long)sa * g.Q + ql]) * h;
+      if (pb.NB == 2) Gb[li] = T(grad[(long long)sb * g.Q + ql]) * h;
+    } else {
+      T acc = -dmp * h;
       for (int s = 0; s < M; ++s) {
-        const int up = tb.up[e * 3 + s];
-        const int dn = tb.dn[e * 3 + s];
-        if (up < 0 && dn < 0) continue;
-        const double vpp = tb.Vp[s * kTab + (ql / g.QS[s]) % g.Nq[s]] *
-                           tb.pg[s * kTab + (pix / g.PS[s]) % g.Np[s]];
-        if (dn >= 0) acc += T(0.5 * tb.tc[e * 3 + s] * vpp) * X[(long long)dn * E + rel0 + j];
-        if (up >= 0) acc -= T(g.bm[s] * vpp) * X[(long long)up * E + rel0 + j];
+        const T hu = up[s] >= 0 ? X[(long long)up[s] * E + rel] : T(0);
+        const T hd = dn[s] >= 0 ? X[(long long)dn[s] * E + rel] : T(0);
+        const double vp = tb.Vp[s * kTab + (ql / g.QS[s]) % g.Nq[s]];
+        acc += T(vp * ps[s] * 0.5 * tc[s]) * hd - T(vp * ps[s] * g.bm[s]) * hu;
+        if (s == sa || (pb.NB == 2 && s == sb)) {
+          const T G = T(tb.F[(long long)s * g.Q + ql]) * h + T(vp) * (hu + T(cc[s]) * hd);
+          if (s == sa)
+            Ga[li] = G;
+          else
+            Gb[li] = G;
+        }
       }
-      ACC[j + j / NpM] = acc;
+      pw[k] = acc;
     }
   }
+  __syncthreads();
 
-  // ---- derivatives along the block axes --------------------------------------
-  for (int ax = 0; ax < pb.NB; ++ax) {
-    const int s = M - 1 - ax;  // p_M first, then p_{M-1}
-    const int Ns = g.Np[s];
-    if (PERTURB) {
-      for (int j = tid; j < npts; j += bd) {
-        const int ql = (b0 + j / B) / bpq;
-        G[j + j / NpM] = T(grad[(long long)s * g.Q + ql]) * X[off0 + j];
-      }
-    } else {
-      const int up = tb.up[e * 3 + s];
-      const int dn = tb.dn[e * 3 + s];
-      const double cc = tb.cc[e * 3 + s];
-      for (int j = tid; j < npts; j += bd) {
-        const int ql = (b0 + j / B) / bpq;
-        const double vp = tb.Vp[s * kTab + (ql / g.QS[s]) % g.Nq[s]];
-        T Gv = T(tb.F[(long long)s * g.Q + ql]) * X[off0 + j];
-        if (up >= 0) Gv += T(vp) * X[(long long)up * E + rel0 + j];
-        if (dn >= 0) Gv += T(vp * cc) * X[(long long)dn * E + rel0 + j];
-        G[j + j / NpM] = Gv;
-      }
-    }
-    __syncthreads();
-    const T ca = T(g.dp_ca[s]), cb = T(g.dp_cb[s]);
-    const int nlines = npts / Ns;
-    for (int l = tid; l < nlines; l += bd) {
-      int base, stride;
-      if (ax == 0) {  // rows of p_M, contiguous
-        base = l * (NpM + 1);
+  // ---- phase 2: rows of Ga and columns of Gb ------------------------------------
+  {
+    const int nla = nrows;
+    const int nlb = pb.NB == 2 ? nbt * cols : 0;
+    for (int l = tid; l < nla + nlb; l += blockDim.x) {
+      T *G;
+      int base, stride, N;
+      T ca, cb;
+      if (l < nla) {
+        G = Ga;
+        base = l * cp;
         stride = 1;
-      } else {        // columns of p_{M-1}: stride one padded row
-        const int col = l % NpM;
-        const int blk = l / NpM;
-        base = blk * pb.rows * (NpM + 1) + col;
-        stride = NpM + 1;
+        N = cols;
+        ca = T(g.dp_ca[sa]);
+        cb = T(g.dp_cb[sa]);
+      } else {
+        const int lb = l - nla;
+        const int blk = lb / cols;
+        const int c = lb - blk * cols;
+        G = Gb;
+        base = blk * rows * cp + c;
+        stride = cp;
+        N = rows;
+        ca = T(g.dp_ca[sb]);
+        cb = T(g.dp_cb[sb]);
       }
       T f[NMAX];
 #pragma unroll
-      for (int i = 0; i < NMAX; ++i) f[i] = (i < Ns) ? G[base + i * stride] : T(0);
-      compact_deriv<T, NMAX>(f, Ns, ca, cb);
+      for (int i = 0; i < NMAX; ++i) f[i] = (i < N) ? G[base + i * stride] : T(0);
+      compact_deriv<T, NMAX>(f, N, ca, cb);
 #pragma unroll
       for (int i = 0; i < NMAX; ++i)
-        if (i < Ns) ACC[base + i * stride] += f[i];
+        if (i < N) G[base + i * stride] = f[i];
     }
-    __syncthreads();
   }
-  for (int j = tid; j < npts; j += bd) out[off0 + j] = ACC[j + j / NpM];
+  __syncthreads();
+
+  // ---- phase 3 ----------------------------------------------------------------
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int R = rg + k * pb.RG;
+    if (!owner || R >= nrows) continue;
+    const int blk = R / rows;
+    const int r = R - blk * rows;
+    const int rel = (b0 + blk) * pb.B + r * cols + col;
+    const int li = R * cp + col;
+    T v = pw[k] + Ga[li];
+    if (pb.NB == 2) v += Gb[li];
+    out[eoff + rel] = v;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -543,6 +581,48 @@ k_check_finite(const T *__restrict__ W, const long long n, int *__restrict__ fla
     bad |= !(v - v == 0.0);
   }
   if (bad) flag[0] = 1;  // benign race: every writer stores 1
+}
+
+// Discrete Fourier sums of the spectra, Eqs. (1DIR_Raman) and (2DThz_Raman),
+// rectangle rule with weight 1 at t = 0.  Twiddles exp(sign 2 pi i k j / n)
+// use the exact reduction (k j mod n) / n before sincospi.
+//   out[row][k] = sum_j exp(sign 2 pi i k j / n) in[row][j]   (complex in/out)
+__global__ void __launch_bounds__(256)
+k_dft_rows(const double2 *__restrict__ in, double2 *__restrict__ out, const int rows, const int n,
+           const int in_stride, const int in_step, const int out_stride, const int out_step,
+           const double sign) {
+  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (id >= (long long)rows * n) return;
+  const int row = (int)(id / n);
+  const int k = (int)(id - (long long)row * n);
+  double re = 0.0, im = 0.0;
+  for (int j = 0; j < n; ++j) {
+    const long long kj = ((long long)k * j) % n;
+    double sv, cv;
+    sincospi(2.0 * (double)kj / (double)n, &sv, &cv);
+    sv *= sign;
+    const double2 v = in[(long long)row * in_stride + (long long)j * in_step];
+    re += v.x * cv - v.y * sv;
+    im += v.x * sv + v.y * cv;
+  }
+  out[(long long)row * out_stride + (long long)k * out_step] = make_double2(re, im);
+}
+
+// real input -> complex (imaginary part 0)
+__global__ void __launch_bounds__(256)
+k_to_complex(const double *__restrict__ in, double2 *__restrict__ out, const long long n) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = make_double2(in[i], 0.0);
+}
+
+// I = scale * omega_k * Im(z)  (omega == nullptr: omega_k = 1)
+__global__ void __launch_bounds__(256)
+k_spectrum_out(const double2 *__restrict__ z, const long long n, const int n_fast, const double scale,
+               const double dw, const int with_omega, double *__restrict__ I) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double w = with_omega ? dw * (double)(i % n_fast) : 1.0;
+  I[i] = scale * w * z[i].y;
 }
 
 // dst = src, 16-byte vectors

@@ -181,3 +181,22 @@ def test_two_mode_full_size_response_2d_sampled(pk):
         got = s.response_2d(w["A"], w["B"], w["C"], 64, 256, 1, 1, w["dt"])
     assert np.all(np.isfinite(got))
     assert rel_l2(got[:4, cols], ref[:4, cols]) < FP64_TOL
+
+
+def test_spectra_parity(pk):
+    """Device Fourier sums of Eqs. (1DIR_Raman), (2DThz_Raman) against the
+    oracle's plain sums, on seeded signals of the response shapes."""
+    say("[spectra]")
+    rng = np.random.default_rng(9)
+    R1 = rng.standard_normal(500)
+    om_ref, I_ref = orc.spectrum_1d(R1, 0.005)
+    om, I = pk.spectrum_1d(R1, 0.005)
+    assert rel_l2(om, om_ref) < 1e-14
+    assert rel_l2(I, I_ref) < 1e-12
+    R2 = rng.standard_normal((256, 64))
+    _, _, I2_ref = orc.spectrum_2d(R2, 0.005, 0.005)
+    I2 = pk.spectrum_2d(R2, 0.005, 0.005)
+    assert rel_l2(I2, I2_ref) < 1e-12
+    R3 = rng.standard_normal((7, 5))  # ragged, odd sizes
+    _, _, I3_ref = orc.spectrum_2d(R3, 0.3, 0.1)
+    assert rel_l2(pk.spectrum_2d(R3, 0.3, 0.1), I3_ref) < 1e-12
