@@ -94,6 +94,9 @@ def main(argv=None):
     ap.add_argument("--timing-every", type=int, default=64,
                     help="bracket every k-th RK4 step's launches with HIP events")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--batch", type=int, default=1, help="t1 branches propagated together")
+    ap.add_argument("--precision", choices=["f64", "f32"], default="f64",
+                    help="type of the propagated t1-branch states")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", choices=["bench", "kernels", "rk4"], default="bench",
                     help="kernels: a few RK4 steps of the workload plus a plain copy of known "
@@ -113,11 +116,14 @@ def main(argv=None):
     import workloads as wl
 
     w = wl.workload(args.workload)
-    assert w["kind"] == "2d", "the benchmark runs a 2D-response workload"
     dt = float(w["dt"])
-    steps_per = rk4_steps(w)
+    if args.mode == "bench" and w["kind"] != "2d":
+        print(f"bench mode needs a 2D-response workload ({args.workload} is {w['kind']})", file=sys.stderr)
+        return 2
+    steps_per = rk4_steps(w) if w["kind"] == "2d" else int(w["eq_steps"]) + int(w["n_t"]) - 1
     torch.cuda.init()
-    solver = pk.Solver(pk.params_from_workload(w))
+    prec = pk.CHFPE_FP32 if args.precision == "f32" else pk.CHFPE_FP64
+    solver = pk.Solver(pk.params_from_workload(w, precision=prec, batch=args.batch))
     S = solver.count
     log(f"[bench] workload={args.workload} values/state={S} rk4_steps/step={steps_per}")
 
@@ -132,13 +138,12 @@ def main(argv=None):
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         kt = solver.kernel_times()
-        kb = solver.kernel_bytes()
         print(json.dumps({"mode": "rk4", "workload": args.workload, "rk4_steps": args.rk4_steps,
                           "ms_per_rk4_step": 1000 * el / args.rk4_steps,
                           "updates_per_s": S * args.rk4_steps / el,
                           "alg_frac_16pass": 16 * 8 * S * args.rk4_steps / el / 1e9 / HBM_PEAK_GBPS,
                           "env": {k: v for k, v in os.environ.items() if k.startswith("CHFPE_TUNE")},
-                          "kernels": {k: {"ms": v[1], "GBps": kb[k] / (v[1] * 1e-3) / 1e9}
+                          "kernels": {k: {"ms": v[1], "GBps": v[2] / (v[1] * 1e-3) / 1e9}
                                       for k, v in kt.items() if v[0] > 0}}), flush=True)
         solver.close()
         return 0
@@ -156,8 +161,7 @@ def main(argv=None):
             pk.stream_copy(dst, src, nbytes)
         torch.cuda.synchronize()
         print(json.dumps({"mode": "kernels", "workload": args.workload, "rk4_steps": args.rk4_steps,
-                          "values_per_state": S, "copy_bytes": nbytes, "copies": 3,
-                          "kernel_bytes": solver.kernel_bytes()}), flush=True)
+                          "values_per_state": S, "copy_bytes": nbytes, "copies": 3}), flush=True)
         solver.close()
         return 0
 
@@ -177,7 +181,7 @@ def main(argv=None):
     torch.cuda.synchronize()
 
     times = []
-    kcount, ktime = {}, {}
+    kcount, ktime, kbyte = {}, {}, {}
     for i in range(args.steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -185,22 +189,21 @@ def main(argv=None):
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
         # the events of this step's context (read before the next rebuild)
-        for k, (cnt, mean) in solver.kernel_times().items():
+        for k, (cnt, mean, mb) in solver.kernel_times().items():
             kcount[k] = kcount.get(k, 0) + cnt
             ktime[k] = ktime.get(k, 0.0) + cnt * mean
+            kbyte[k] = kbyte.get(k, 0.0) + cnt * mb
         log(f"[bench] step {i + 1}/{args.steps}: {times[-1]:.3f} s")
     kt = {k: (kcount[k], ktime[k] / kcount[k] if kcount[k] else 0.0) for k in kcount}
-    kb = solver.kernel_bytes()
+    kb = {k: (kbyte[k] / kcount[k] if kcount[k] else 0.0) for k in kcount}
     total = float(sum(times))
     ms_per_step = 1000.0 * total / args.steps
     updates = float(S) * steps_per * args.steps
     value = updates / total
 
-    # roofline of the dominant kernel
-    lps = launches_per_rk4_step(int(w["M"]))
-    share = {k: kt[k][1] * n for k, n in lps.items() if k in kt and kt[k][0] > 0}
+    # roofline of the dominant kernel (largest share of the timed launches' time)
+    share = {k: kt[k][0] * kt[k][1] for k in kt if kt[k][0] > 0}
     roofline = None
-    step_ms = sum(share.values())
     if share:
         dom = max(share, key=share.get)
         mean_ms = kt[dom][1]
@@ -210,7 +213,8 @@ def main(argv=None):
         if os.path.exists(tf):
             try:
                 rec = json.load(open(tf))
-                if rec.get("source_hash") == source_hash() and dom in rec.get("bytes_per_launch", {}):
+                if (rec.get("source_hash") == source_hash() and dom in rec.get("bytes_per_launch", {})
+                        and rec.get("batch") == args.batch and rec.get("precision") == args.precision):
                     traffic = float(rec["bytes_per_launch"][dom])
             except (OSError, ValueError):
                 traffic = None
@@ -218,12 +222,13 @@ def main(argv=None):
                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                     "traffic": traffic, "mean_ms": mean_ms, "bytes_per_launch": kb[dom],
                     "timed_launches": kt[dom][0]}
-    # whole RK4 step against the 16-pass algorithmic floor
-    step_alg = None
-    if step_ms > 0:
-        step_alg = {"ms_per_rk4_step": step_ms,
-                    "algorithmic_GBps": 16 * 8 * S / (step_ms * 1e-3) / 1e9,
-                    "frac": 16 * 8 * S / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS}
+    # whole hot path against the 16-pass algorithmic floor of classical RK4
+    tb = 4 if args.precision == "f32" else 8
+    n_branch = int(w["n_t1"]) * (int(w["n_t2"]) - 1) * int(w["stride2"])
+    n_fp64 = steps_per - n_branch
+    alg_bytes = 16.0 * S * (8 * n_fp64 + tb * n_branch) * args.steps
+    step_alg = {"algorithmic_GBps": alg_bytes / total / 1e9,
+                "frac": alg_bytes / total / 1e9 / HBM_PEAK_GBPS}
 
     cpu = None
     parity = None
@@ -244,13 +249,14 @@ def main(argv=None):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": args.precision,
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: 2 modes, 32^4 (q,p) grid, depth 3 (10 elements), "
                                f"equilibration 4000 + 2D THz-Raman 64 t1 x 256 t2 RK4 steps, dt {dt}",
-                   "values_per_state": S, "rk4_steps_per_step": steps_per},
+                   "values_per_state": S, "rk4_steps_per_step": steps_per,
+                   "branch_batch": args.batch, "branch_precision": args.precision},
         "roofline": roofline,
-        "rk4_step_roofline": step_alg,
+        "path_roofline_16pass": step_alg,
         "cpu_baseline": cpu,
         "spectrum_time_s": ms_per_step / 1000.0,
         "parity_rel_l2_vs_oracle": parity,

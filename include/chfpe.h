@@ -57,7 +57,14 @@ enum { CHFPE_FP64 = 0, CHFPE_FP32 = 1 };
  *   Drude bath per mode: zeta_s, gamma_s (Eq. (eq:drude)); beta = 1/T.
  *   K: hierarchy depth, elements {n : |n| <= K} (Eq. (eq:HEOM)).
  *   Nq/Np, Lq/Lp: points and half-width of the q_s and p_s axes.
- *   precision: CHFPE_FP64 (the only value accepted by this build).
+ *   precision: type of the t1-branch states of chfpe_response_2d.  With
+ *     CHFPE_FP32 their right-hand sides and RK4 updates are FP32, while the
+ *     equilibration, the t1 trajectory U, both excitations (A^x, B^x) and
+ *     every reduction stay FP64.  Everything else is FP64.
+ *   batch: t1 branches propagated together by chfpe_response_2d (0 = 1);
+ *     with batch > 1 or CHFPE_FP32, branches run in waves of `batch` states
+ *     (batch x 5 extra state buffers of the branch type in the workspace),
+ *     each wave's t2 loop as one captured HIP graph.
  * Limits: 1 <= M <= 3, 0 <= K <= 12, 5 <= N <= 48 on every axis, all
  * masses, beta, L > 0, one element below 2^31 points, and
  * exp(-beta H_sys/2) representable (> 1e-150) everywhere on the grid.
@@ -82,6 +89,7 @@ typedef struct {
   double gamma[3];
   double beta;
   int32_t precision;
+  int32_t batch;
 } chfpe_params;
 
 /* Optical operator X(q) = sum_s lin_s q_s + 1/2 sum_{s,s'} quad_ss' q_s q_s'
@@ -94,8 +102,8 @@ typedef struct {
 typedef struct chfpe_ctx chfpe_ctx;
 
 /* Bytes of device workspace chfpe_setup needs for these parameters (tables,
- * eight state-sized buffers, reduction scratch), or 0 if the parameters are
- * invalid.  The caller may allocate it (e.g. as a torch tensor) and pass it
+ * seven FP64 state buffers, the batched branch buffers, reduction scratch),
+ * or 0 if the parameters are invalid.  The caller may allocate it (e.g. as a torch tensor) and pass it
  * to chfpe_setup. */
 size_t chfpe_workspace_bytes(const chfpe_params *p);
 
@@ -187,18 +195,17 @@ int chfpe_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream
 
 /* Per-kernel timing with HIP events on the context's stream: every
  * `every`-th RK4 step (0 turns timing off) each launch of that step is
- * bracketed by events.  chfpe_kernel_times reports, for each kernel kind,
- * the number of timed launches and their mean duration in milliseconds and
- * the kind's name; it synchronizes the stream.  Returns the number of kinds
- * written (at most max_kinds). */
+ * bracketed by events; while timing is on, 2D-response waves are issued
+ * directly instead of as HIP graphs.  chfpe_kernel_times reports, for each
+ * kernel kind, the number of timed launches, their mean duration in
+ * milliseconds, their mean algorithmic bytes (each input state read once and
+ * each output state written once) and the kind's name; launches that carry
+ * several branch states are separate kinds ("batch_" names).  It
+ * synchronizes the stream and returns the number of kinds written (at most
+ * max_kinds).  Any output pointer may be NULL. */
 int chfpe_set_kernel_timing(chfpe_ctx *ctx, int32_t every);
 int chfpe_kernel_times(chfpe_ctx *ctx, int32_t max_kinds, int64_t *counts, double *mean_ms,
-                       const char **names);
-
-/* Algorithmic bytes per launch of each kernel kind (same order and names as
- * chfpe_kernel_times); returns the number of kinds written. */
-int chfpe_kernel_bytes(const chfpe_ctx *ctx, int32_t max_kinds, double *bytes,
-                       const char **names);
+                       double *mean_bytes, const char **names);
 
 /* Message of the last error on this context (or of the last failed
  * chfpe_setup on this thread when ctx is NULL); never NULL. */

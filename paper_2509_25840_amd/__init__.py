@@ -38,7 +38,7 @@ class Params(ctypes.Structure):
         ("m", _d3), ("omega", _d3), ("g3", _d3), ("g4", _d3),
         ("g2", _d33), ("g21", _d33), ("g12", _d33),
         ("V_LL", _d3), ("V_SL", _d3), ("zeta", _d3), ("gamma", _d3),
-        ("beta", ctypes.c_double), ("precision", ctypes.c_int32),
+        ("beta", ctypes.c_double), ("precision", ctypes.c_int32), ("batch", ctypes.c_int32),
     ]
 
 
@@ -104,10 +104,8 @@ def lib():
     L.chfpe_stream_copy.restype = ctypes.c_int
     L.chfpe_set_kernel_timing.argtypes = [vp, i32]
     L.chfpe_set_kernel_timing.restype = ctypes.c_int
-    L.chfpe_kernel_times.argtypes = [vp, i32, ctypes.POINTER(i64), dp, ctypes.POINTER(ctypes.c_char_p)]
+    L.chfpe_kernel_times.argtypes = [vp, i32, ctypes.POINTER(i64), dp, dp, ctypes.POINTER(ctypes.c_char_p)]
     L.chfpe_kernel_times.restype = ctypes.c_int
-    L.chfpe_kernel_bytes.argtypes = [vp, i32, dp, ctypes.POINTER(ctypes.c_char_p)]
-    L.chfpe_kernel_bytes.restype = ctypes.c_int
     L.chfpe_last_error.argtypes = [vp]
     L.chfpe_last_error.restype = ctypes.c_char_p
     L.chfpe_destroy.argtypes = [vp]
@@ -116,8 +114,11 @@ def lib():
     return L
 
 
-def params_from_workload(w: dict, precision: int = CHFPE_FP64) -> Params:
-    """chfpe_params from a workload dict (see ``workloads``)."""
+def params_from_workload(w: dict, precision=None, batch: int = 0) -> Params:
+    """chfpe_params from a workload dict (see ``workloads``); precision
+    defaults to the workload's ("f32" -> CHFPE_FP32, else CHFPE_FP64)."""
+    if precision is None:
+        precision = CHFPE_FP32 if w.get("precision") == "f32" else CHFPE_FP64
     p = Params()
     M = int(w["M"])
     p.M, p.K = M, int(w["K"])
@@ -134,6 +135,7 @@ def params_from_workload(w: dict, precision: int = CHFPE_FP64) -> Params:
             p.g12[s][t] = float(w["g12"][s][t])
     p.beta = float(w["beta"])
     p.precision = int(precision)
+    p.batch = int(batch)
     return p
 
 
@@ -313,20 +315,13 @@ class Solver:
         self._check(lib().chfpe_set_kernel_timing(self._ctx, int(every)))
 
     def kernel_times(self) -> dict:
-        n = 16
+        """{kind: (timed launches, mean ms, mean algorithmic bytes)}."""
+        n = 32
         counts = (ctypes.c_int64 * n)()
         means = (ctypes.c_double * n)()
+        mbytes = (ctypes.c_double * n)()
         names = (ctypes.c_char_p * n)()
-        k = lib().chfpe_kernel_times(self._ctx, n, counts, means, names)
+        k = lib().chfpe_kernel_times(self._ctx, n, counts, means, mbytes, names)
         if k < 0:
             self._check(k)
-        return {names[i].decode(): (int(counts[i]), float(means[i])) for i in range(k)}
-
-    def kernel_bytes(self) -> dict:
-        n = 16
-        b = (ctypes.c_double * n)()
-        names = (ctypes.c_char_p * n)()
-        k = lib().chfpe_kernel_bytes(self._ctx, n, b, names)
-        if k < 0:
-            self._check(k)
-        return {names[i].decode(): float(b[i]) for i in range(k)}
+        return {names[i].decode(): (int(counts[i]), float(means[i]), float(mbytes[i])) for i in range(k)}

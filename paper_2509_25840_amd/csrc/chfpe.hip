@@ -31,10 +31,13 @@ namespace {
 thread_local std::string g_setup_error = "no error";
 
 constexpr int kPBlockThreads = 256;  // k_pblock workgroup size (upper bound)
-constexpr int kPBlockRPT = 16;       // rows per k_pblock thread
+constexpr int kPBlockRPT = 4;        // rows per k_pblock thread
 constexpr int kQThreadsMax = 512;    // largest k_qpass workgroup
 
-constexpr int kNumKinds = 9;
+// Kernel kinds for event timing; batched launches (several branch states per
+// launch) are kept apart from single-state ones.
+constexpr int kNumBase = 9;
+constexpr int kNumKinds = 2 * kNumBase;
 enum Kind : int {
   K_PBLOCK = 0,
   K_QACC = 1,
@@ -46,13 +49,18 @@ enum Kind : int {
   K_PERTURB = 7,
   K_QOUT = 8
 };
-const char *kKindNames[kNumKinds] = {"pblock_rhs", "qpass_acc", "qpass_rk4_s1", "qpass_rk4_s2",
-                                     "qpass_rk4_s3", "qpass_rk4_s4", "observe", "perturb",
-                                     "qpass_out"};
+const char *kKindNames[kNumKinds] = {
+    "pblock_rhs", "qpass_acc", "qpass_rk4_s1", "qpass_rk4_s2", "qpass_rk4_s3", "qpass_rk4_s4", "observe",
+    "perturb", "qpass_out", "batch_pblock_rhs", "batch_qpass_acc", "batch_qpass_rk4_s1", "batch_qpass_rk4_s2",
+    "batch_qpass_rk4_s3", "batch_qpass_rk4_s4", "batch_observe", "batch_perturb", "batch_qpass_out"};
+// state passes each kind reads plus writes (each input once, each output once)
+const double kKindPasses[kNumBase] = {2, 3, 4, 6, 6, 4, 0.1, 2, 3};
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Derived {
+  int prec = 0, B = 1;    // precision of branch states; branches per wave
+  bool batched = false;   // 2D responses use the batched branch buffers
   int M, K, ne;
   int Nq[3], Np[3];
   int Q, P;
@@ -73,10 +81,17 @@ bool derive(const chfpe_params *p, Derived &d, std::string &err) {
     err = "K must be in [0, 12]";
     return false;
   }
-  if (p->precision != CHFPE_FP64) {
-    err = "only CHFPE_FP64 is supported by this build";
+  if (p->precision != CHFPE_FP64 && p->precision != CHFPE_FP32) {
+    err = "precision must be CHFPE_FP64 or CHFPE_FP32";
     return false;
   }
+  if (p->batch < 0 || p->batch > 1024) {
+    err = "batch must be in [0, 1024]";
+    return false;
+  }
+  d.prec = p->precision;
+  d.B = p->batch > 0 ? p->batch : 1;
+  d.batched = d.B > 1 || d.prec == CHFPE_FP32;
   d.M = p->M;
   d.K = p->K;
   d.Q = 1;
@@ -147,8 +162,9 @@ bool derive(const chfpe_params *p, Derived &d, std::string &err) {
 
 // Workspace layout (byte offsets, 256-aligned).
 struct Layout {
-  size_t F, Vp, pm, pg, gA, gB, Cw, wp, sq, sp, up, dn, cc, tc, damp, partial, scal, flag;
+  size_t F, VpQ, Vp, pm, pg, gA, gB, Cw, wp, sq, sp, up, dn, cc, tc, damp, partial, scal, flag;
   size_t bufs[7];
+  size_t bbufs[5];  // batched branch buffers: y, yacc, xa, xb, t (B states each)
   size_t total;
 };
 constexpr int kPartials = 2048;
@@ -162,6 +178,7 @@ Layout layout(const Derived &d) {
     return at;
   };
   L.F = take(sizeof(double) * 3 * d.Q);
+  L.VpQ = take(sizeof(double) * 3 * d.Q);
   L.Vp = take(sizeof(double) * 3 * kTab);
   L.pm = take(sizeof(double) * 3 * kTab);
   L.pg = take(sizeof(double) * 3 * kTab);
@@ -180,6 +197,8 @@ Layout layout(const Derived &d) {
   L.scal = take(sizeof(double) * 16);
   L.flag = take(sizeof(int) * 16);
   for (int i = 0; i < 7; ++i) L.bufs[i] = take(sizeof(double) * (size_t)d.S);
+  const size_t tsz = d.prec == CHFPE_FP32 ? sizeof(float) : sizeof(double);
+  for (int i = 0; i < 5; ++i) L.bbufs[i] = d.batched ? take(tsz * (size_t)d.S * d.B) : 0;
   L.total = o;
   return L;
 }
@@ -216,9 +235,13 @@ struct chfpe_ctx {
   hipStream_t stream = nullptr;
   unsigned char *ws = nullptr;
   bool own_ws = false;
-  double *F, *Vp, *pm, *pg, *gA, *gB, *Cw, *wp, *sq, *sp, *cc, *tc, *damp, *partial, *scal;
+  double *F, *VpQ, *Vp, *pm, *pg, *gA, *gB, *Cw, *wp, *sq, *sp, *cc, *tc, *damp, *partial, *scal;
   int *up, *dn, *flag;
   double *weq, *u, *y, *yacc, *xa, *xb, *t;
+  void *bb[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // batched y, yacc, xa, xb, t
+  // cached graph of one wave's t2 loop
+  hipGraphExec_t wave_graph = nullptr;
+  long long wave_key[6] = {0, 0, 0, 0, 0, 0};
   bool has_eq = false;
   double dV = 1.0;
   std::vector<double> qgrid[3], pgrid[3];
@@ -229,6 +252,8 @@ struct chfpe_ctx {
   std::string err = "no error";
   int tune_pb_nb = 0;   // blocks per k_pblock task (0: automatic)
   int tune_q_pc = 0;    // run positions per two-axis k_qpass tile (0: automatic)
+  bool capturing = false;  // a HIP graph is being captured: no event timing
+  bool use_graphs = true;
   // kernel timing
   int timing_every = 0;
   long long step_counter = 0;
@@ -236,11 +261,13 @@ struct chfpe_ctx {
   struct Pending {
     hipEvent_t a, b;
     int kind;
+    double bytes;
   };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> event_pool;
   long long kcount[kNumKinds] = {0};
   double ktime[kNumKinds] = {0};
+  double kbytes[kNumKinds] = {0};
 };
 
 namespace {
@@ -370,6 +397,7 @@ void make_geom(chfpe_ctx *c) {
   std::memset(&g, 0, sizeof(g));
   g.M = d.M;
   g.ne = d.ne;
+  g.nbatch = 1;
   g.Q = d.Q;
   g.P = d.P;
   g.E = d.E;
@@ -448,11 +476,11 @@ void plan_two(chfpe_ctx *c, int a, int b, int run, std::vector<int> rest, QPass 
   const int Na = axis_len(d, a), Nb = axis_len(d, b);
   int pc = c->tune_q_pc > 0 ? c->tune_q_pc : 16;
   const size_t lds_cap = c->tune_q_pc > 0 ? 160 * 1024 : 80 * 1024;
-  while (pc > 1 && ((size_t)Na * Nb * pc * sizeof(double) > lds_cap || std::max(Na, Nb) * pc > kQThreadsMax))
+  while (pc > 1 && ((size_t)Na * (Nb + 1) * pc * sizeof(double) > lds_cap || std::max(Na, Nb) * pc > kQThreadsMax))
     pc /= 2;
   out = make_qpass(c, a, b, run, rest, pc);
   thr = (std::max(Na, Nb) * out.pc + 63) / 64 * 64;
-  lds = (size_t)Na * Nb * out.pc * sizeof(double);
+  lds = (size_t)Na * (Nb + 1) * out.pc * sizeof(double);
   nmax = nmax_bucket(std::max(Na, Nb));
 }
 
@@ -477,6 +505,8 @@ void plan(chfpe_ctx *c) {
   pb.nblocks = (int)(d.E / pb.B);
   pb.bpq = d.P / pb.B;
   pb.RG = std::max(1, kPBlockThreads / pb.cols);
+  if (pb.NB == 2)  // row groups divide the rows: the block of a row batch is uniform
+    while (pb.rows % pb.RG) --pb.RG;
   // lines per task ~ threads; rows per thread <= kPBlockRPT; LDS <= ~80 KB
   const size_t blk_bytes = (size_t)pb.NB * pb.rows * (NpM + 1) * sizeof(double);
   const int lines_per_blk = pb.rows + (pb.NB == 2 ? pb.cols : 0);
@@ -486,10 +516,12 @@ void plan(chfpe_ctx *c) {
     --nb;
   nb = std::min(nb, pb.nblocks);
   pb.nb = nb;
-  pb.tileP = nb * pb.rows * (NpM + 1);
+  // every thread row index rg + k RG (k < RPT) has an LDS slot
+  const int tile_rows = std::max(nb * pb.rows, pb.RG * kPBlockRPT);
+  pb.tileP = tile_rows * (NpM + 1);
   pb.ntasks = d.ne * ((pb.nblocks + nb - 1) / nb);
   pb.nblk = pad8(pb.ntasks);
-  ln.pb_lds = (size_t)nb * blk_bytes;
+  ln.pb_lds = (size_t)pb.NB * pb.tileP * sizeof(double);
   ln.pb_threads = pb.RG * pb.cols;
   ln.pb_nmax = nmax_bucket(std::max(pb.rows, pb.cols));
   // strided-axis passes
@@ -539,6 +571,7 @@ int drain_timing(chfpe_ctx *c) {
     if (hipEventElapsedTime(&ms, pd.a, pd.b) == hipSuccess) {
       c->kcount[pd.kind] += 1;
       c->ktime[pd.kind] += ms;
+      c->kbytes[pd.kind] += pd.bytes;
     }
     c->event_pool.push_back(pd.a);
     c->event_pool.push_back(pd.b);
@@ -547,12 +580,18 @@ int drain_timing(chfpe_ctx *c) {
   return CHFPE_OK;
 }
 
+// Brackets one launch with events when the current RK4 step is timed.
+// nstates x state_bytes is the state data the launch's kind touches per pass
+// (the observe kind reads element 0 only, accounted by its pass factor).
 struct TimedScope {
   chfpe_ctx *c;
   int kind;
+  double bytes;
   hipEvent_t a = nullptr;
-  TimedScope(chfpe_ctx *c_, int k) : c(c_), kind(k) {
-    if (c->timing_now) {
+  TimedScope(chfpe_ctx *c_, int k, int nstates = 1, size_t tsize = sizeof(double))
+      : c(c_), kind(k + (nstates > 1 ? kNumBase : 0)),
+        bytes(kKindPasses[k] * (double)nstates * (double)c_->d.S * (double)tsize) {
+    if (c->timing_now && !c->capturing) {
       a = get_event(c);
       if (a) (void)hipEventRecord(a, c->stream);
     }
@@ -562,7 +601,7 @@ struct TimedScope {
       hipEvent_t b = get_event(c);
       if (b) {
         (void)hipEventRecord(b, c->stream);
-        c->pending.push_back({a, b, kind});
+        c->pending.push_back({a, b, kind, bytes});
       } else {
         c->event_pool.push_back(a);
       }
@@ -577,82 +616,121 @@ void allow_lds(K kern, size_t bytes) {
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int NMAX, bool PERTURB>
-void launch_pblock_n(chfpe_ctx *c, const double *X, double *out, const double *grad) {
+// A launch description for nb states stored back to back (t1 branches).
+struct Batch {
+  Geom g;
+  PBlock pb;
+  QPass qa, qf, qx;
+};
+
+Batch batch_of(const chfpe_ctx *c, int nb) {
+  Batch b;
+  b.g = c->g;
+  b.g.nbatch = nb;
+  b.pb = c->ln.pb;
+  b.pb.ntasks *= nb;
+  b.pb.nblk = pad8(b.pb.ntasks);
+  QPass *q[3] = {&b.qa, &b.qf, &b.qx};
+  const QPass *s[3] = {&c->ln.qa, &c->ln.qf, &c->ln.qx};
+  for (int i = 0; i < 3; ++i) {
+    *q[i] = *s[i];
+    q[i]->ntasks *= nb;
+    q[i]->nblk = pad8(q[i]->ntasks);
+  }
+  return b;
+}
+
+template <typename T, typename TO, int NMAX, int MM, bool PERTURB>
+void launch_pblock_nm(chfpe_ctx *c, const Batch &b, const T *X, TO *out, const double *grad) {
   const Launch &ln = c->ln;
-  auto kern = k_pblock<double, NMAX, kPBlockRPT, PERTURB>;
+  auto kern = k_pblock<T, TO, NMAX, kPBlockRPT, MM, PERTURB>;
   allow_lds(kern, ln.pb_lds);
-  hipLaunchKernelGGL(kern, dim3(ln.pb.nblk), dim3(ln.pb_threads), ln.pb_lds, c->stream, c->g, c->tb, ln.pb,
-                     X, out, grad);
+  hipLaunchKernelGGL(kern, dim3(b.pb.nblk), dim3(ln.pb_threads), ln.pb_lds, c->stream, b.g, c->tb, b.pb, X,
+                     out, grad);
 }
 
-template <bool PERTURB>
-void launch_pblock_t(chfpe_ctx *c, const double *X, double *out, const double *grad) {
+template <typename T, typename TO, int NMAX, bool PERTURB>
+void launch_pblock_n(chfpe_ctx *c, const Batch &b, const T *X, TO *out, const double *grad) {
+  switch (c->d.M) {
+    case 1: launch_pblock_nm<T, TO, NMAX, 1, PERTURB>(c, b, X, out, grad); break;
+    case 2: launch_pblock_nm<T, TO, NMAX, 2, PERTURB>(c, b, X, out, grad); break;
+    default: launch_pblock_nm<T, TO, NMAX, 3, PERTURB>(c, b, X, out, grad); break;
+  }
+}
+
+template <typename T, typename TO, bool PERTURB>
+void launch_pblock_t(chfpe_ctx *c, const Batch &b, const T *X, TO *out, const double *grad) {
   switch (c->ln.pb_nmax) {
-    case 8: launch_pblock_n<8, PERTURB>(c, X, out, grad); break;
-    case 12: launch_pblock_n<12, PERTURB>(c, X, out, grad); break;
-    case 16: launch_pblock_n<16, PERTURB>(c, X, out, grad); break;
-    case 24: launch_pblock_n<24, PERTURB>(c, X, out, grad); break;
-    case 32: launch_pblock_n<32, PERTURB>(c, X, out, grad); break;
-    default: launch_pblock_n<48, PERTURB>(c, X, out, grad); break;
+    case 8: launch_pblock_n<T, TO, 8, PERTURB>(c, b, X, out, grad); break;
+    case 12: launch_pblock_n<T, TO, 12, PERTURB>(c, b, X, out, grad); break;
+    case 16: launch_pblock_n<T, TO, 16, PERTURB>(c, b, X, out, grad); break;
+    case 24: launch_pblock_n<T, TO, 24, PERTURB>(c, b, X, out, grad); break;
+    case 32: launch_pblock_n<T, TO, 32, PERTURB>(c, b, X, out, grad); break;
+    default: launch_pblock_n<T, TO, 48, PERTURB>(c, b, X, out, grad); break;
   }
 }
 
-template <int NMAX, bool TWO, int EPI, int FA, int FB>
-void launch_q_n(chfpe_ctx *c, const QPass &qp, int threads, size_t lds, const double *X, double *Tacc,
-                const double *y, double *yacc, double *xo, const double *grad, double dt) {
-  auto kern = k_qpass<double, NMAX, TWO, EPI, FA, FB>;
+template <typename T, typename TO, int NMAX, bool TWO, int EPI, int FA, int FB>
+void launch_q_n(chfpe_ctx *c, const Batch &b, const QPass &qp, int threads, size_t lds, const T *X, TO *Tacc,
+                const TO *y, TO *yacc, TO *xo, const double *grad, double dt) {
+  auto kern = k_qpass<T, TO, NMAX, TWO, EPI, FA, FB>;
   allow_lds(kern, lds);
-  hipLaunchKernelGGL(kern, dim3(qp.nblk), dim3(threads), lds, c->stream, c->g, c->tb, qp, X, Tacc, y,
-                     yacc, xo, grad, dt);
+  hipLaunchKernelGGL(kern, dim3(qp.nblk), dim3(threads), lds, c->stream, b.g, c->tb, qp, X, Tacc, y, yacc,
+                     xo, grad, dt);
 }
 
-template <bool TWO, int EPI, int FA, int FB>
-void launch_q_t(chfpe_ctx *c, const QPass &qp, int threads, size_t lds, int nmax, const double *X,
-                double *Tacc, const double *y, double *yacc, double *xo, const double *grad, double dt) {
+template <typename T, typename TO, bool TWO, int EPI, int FA, int FB>
+void launch_q_t(chfpe_ctx *c, const Batch &b, const QPass &qp, int threads, size_t lds, int nmax, const T *X,
+                TO *Tacc, const TO *y, TO *yacc, TO *xo, const double *grad, double dt) {
+#define CHFPE_QN(N) launch_q_n<T, TO, N, TWO, EPI, FA, FB>(c, b, qp, threads, lds, X, Tacc, y, yacc, xo, grad, dt)
   switch (nmax) {
-    case 8: launch_q_n<8, TWO, EPI, FA, FB>(c, qp, threads, lds, X, Tacc, y, yacc, xo, grad, dt); break;
-    case 12: launch_q_n<12, TWO, EPI, FA, FB>(c, qp, threads, lds, X, Tacc, y, yacc, xo, grad, dt); break;
-    case 16: launch_q_n<16, TWO, EPI, FA, FB>(c, qp, threads, lds, X, Tacc, y, yacc, xo, grad, dt); break;
-    case 24: launch_q_n<24, TWO, EPI, FA, FB>(c, qp, threads, lds, X, Tacc, y, yacc, xo, grad, dt); break;
-    case 32: launch_q_n<32, TWO, EPI, FA, FB>(c, qp, threads, lds, X, Tacc, y, yacc, xo, grad, dt); break;
-    default: launch_q_n<48, TWO, EPI, FA, FB>(c, qp, threads, lds, X, Tacc, y, yacc, xo, grad, dt); break;
+    case 8: CHFPE_QN(8); break;
+    case 12: CHFPE_QN(12); break;
+    case 16: CHFPE_QN(16); break;
+    case 24: CHFPE_QN(24); break;
+    case 32: CHFPE_QN(32); break;
+    default: CHFPE_QN(48); break;
   }
+#undef CHFPE_QN
 }
 
-// One right-hand-side evaluation of X fused with the stage update EPI.
-template <int EPI>
-void launch_stage(chfpe_ctx *c, const double *X, const double *y, double *yacc, double *xo, double dt) {
+// One right-hand-side evaluation of X (t: partial right-hand side) fused with
+// the stage update EPI; all buffers hold b.g.nbatch states.
+template <typename T, int EPI>
+void launch_stage(chfpe_ctx *c, const Batch &b, const T *X, T *t, const T *y, T *yacc, T *xo, double dt) {
   const Launch &ln = c->ln;
   {
-    TimedScope ts(c, K_PBLOCK);
-    launch_pblock_t<false>(c, X, c->t, nullptr);
+    TimedScope ts(c, K_PBLOCK, b.g.nbatch, sizeof(T));
+    launch_pblock_t<T, T, false>(c, b, X, t, nullptr);
   }
   if (ln.has_qa) {
-    TimedScope ts(c, K_QACC);
-    launch_q_t<true, EPI_ACC, FQ, FQ>(c, ln.qa, ln.qa_threads, ln.qa_lds, ln.qa_nmax, X, c->t, nullptr,
-                                      nullptr, nullptr, nullptr, dt);
+    TimedScope ts(c, K_QACC, b.g.nbatch, sizeof(T));
+    launch_q_t<T, T, true, EPI_ACC, FQ, FQ>(c, b, b.qa, ln.qa_threads, ln.qa_lds, ln.qa_nmax, X, t, nullptr,
+                                            nullptr, nullptr, nullptr, dt);
   }
   const int kind = EPI == EPI_S1 ? K_QS1 : EPI == EPI_S2 ? K_QS2 : EPI == EPI_S3 ? K_QS3
                  : EPI == EPI_S4 ? K_QS4 : K_QOUT;
-  TimedScope ts(c, kind);
+  TimedScope ts(c, kind, b.g.nbatch, sizeof(T));
   if (c->d.M == 1)
-    launch_q_t<false, EPI, FQ, FQ>(c, ln.qf, ln.qf_threads, 0, ln.qf_nmax, X, c->t, y, yacc, xo, nullptr, dt);
+    launch_q_t<T, T, false, EPI, FQ, FQ>(c, b, b.qf, ln.qf_threads, 0, ln.qf_nmax, X, t, y, yacc, xo, nullptr, dt);
   else if (c->d.M == 2)
-    launch_q_t<true, EPI, FQ, FQ>(c, ln.qf, ln.qf_threads, ln.qf_lds, ln.qf_nmax, X, c->t, y, yacc, xo,
-                                  nullptr, dt);
+    launch_q_t<T, T, true, EPI, FQ, FQ>(c, b, b.qf, ln.qf_threads, ln.qf_lds, ln.qf_nmax, X, t, y, yacc, xo,
+                                        nullptr, dt);
   else
-    launch_q_t<true, EPI, FQ, FP>(c, ln.qf, ln.qf_threads, ln.qf_lds, ln.qf_nmax, X, c->t, y, yacc, xo,
-                                  nullptr, dt);
+    launch_q_t<T, T, true, EPI, FQ, FP>(c, b, b.qf, ln.qf_threads, ln.qf_lds, ln.qf_nmax, X, t, y, yacc, xo,
+                                        nullptr, dt);
 }
 
-// out = X^x W for every element (grad: dX/dq_s table)
-void launch_perturb(chfpe_ctx *c, const double *W, double *out, const double *grad) {
+// out = X^x W for every element of one state, arithmetic in FP64
+// (grad: dX/dq_s table); out may be FP64 or the propagation type.
+template <typename TO>
+void launch_perturb(chfpe_ctx *c, const double *W, TO *out, const double *grad) {
   TimedScope ts(c, K_PERTURB);
-  launch_pblock_t<true>(c, W, out, grad);
+  const Batch b = batch_of(c, 1);
+  launch_pblock_t<double, TO, true>(c, b, W, out, grad);
   if (c->ln.has_qx)
-    launch_q_t<false, EPI_ACC, FX, FQ>(c, c->ln.qx, c->ln.qx_threads, 0, c->ln.qx_nmax, W, out, nullptr,
-                                       nullptr, nullptr, grad, 0.0);
+    launch_q_t<double, TO, false, EPI_ACC, FX, FQ>(c, b, b.qx, c->ln.qx_threads, 0, c->ln.qx_nmax, W, out,
+                                                   nullptr, nullptr, nullptr, grad, 0.0);
 }
 
 int last_launch_error(chfpe_ctx *c) {
@@ -661,19 +739,27 @@ int last_launch_error(chfpe_ctx *c) {
   return CHFPE_OK;
 }
 
-// n classical RK4 steps on buffer yb (in place).
-int rk4(chfpe_ctx *c, double *yb, long long nsteps, double dt) {
+// The buffers of one classical RK4 integration: y (in place), yacc, the
+// alternating stage inputs xa/xb, and the partial right-hand side t.
+template <typename T>
+struct RK4Bufs {
+  T *y, *yacc, *xa, *xb, *t;
+};
+
+// n classical RK4 steps on b.g.nbatch states (in place).
+template <typename T>
+int rk4(chfpe_ctx *c, const Batch &b, const RK4Bufs<T> &r, long long nsteps, double dt) {
   for (long long st = 0; st < nsteps; ++st) {
     c->timing_now = c->timing_every > 0 && (c->step_counter % c->timing_every) == 0;
     ++c->step_counter;
     // stage 1: k1 = f(y); yacc = y + dt/6 k1; xa = y + dt/2 k1
-    launch_stage<EPI_S1>(c, yb, yb, c->yacc, c->xa, dt);
+    launch_stage<T, EPI_S1>(c, b, r.y, r.t, r.y, r.yacc, r.xa, dt);
     // stage 2: k2 = f(xa); yacc += dt/3 k2; xb = y + dt/2 k2
-    launch_stage<EPI_S2>(c, c->xa, yb, c->yacc, c->xb, dt);
+    launch_stage<T, EPI_S2>(c, b, r.xa, r.t, r.y, r.yacc, r.xb, dt);
     // stage 3: k3 = f(xb); yacc += dt/3 k3; xa = y + dt k3
-    launch_stage<EPI_S3>(c, c->xb, yb, c->yacc, c->xa, dt);
+    launch_stage<T, EPI_S3>(c, b, r.xb, r.t, r.y, r.yacc, r.xa, dt);
     // stage 4: k4 = f(xa); y = yacc + dt/6 k4
-    launch_stage<EPI_S4>(c, c->xa, nullptr, c->yacc, yb, dt);
+    launch_stage<T, EPI_S4>(c, b, r.xa, r.t, nullptr, r.yacc, r.y, dt);
     if (c->timing_now) {
       c->timing_now = false;
       if (c->pending.size() > 4096) {
@@ -685,13 +771,108 @@ int rk4(chfpe_ctx *c, double *yb, long long nsteps, double dt) {
   return last_launch_error(c);
 }
 
+// FP64 single-state integration on buffer yb
+int rk4(chfpe_ctx *c, double *yb, long long nsteps, double dt) {
+  const Batch b = batch_of(c, 1);
+  return rk4<double>(c, b, RK4Bufs<double>{yb, c->yacc, c->xa, c->xb, c->t}, nsteps, dt);
+}
+
+// dst[b * dstride] = <C>(state b of W), b < nb (Cw holds the C table)
+template <typename T>
+void observe_batch(chfpe_ctx *c, const T *W, int nb, double *dst, int dstride) {
+  TimedScope ts(c, K_OBSERVE, nb, sizeof(T));
+  const int per = std::max(1, std::min(kPartials / nb, (int)((c->d.E + 255) / 256)));
+  hipLaunchKernelGGL((k_reduce_w0<T>), dim3(per, nb), dim3(256), 0, c->stream, W, c->Cw, c->wp, c->d.Q, c->d.P,
+                     c->partial, (long long)c->d.S);
+  hipLaunchKernelGGL(k_reduce_final, dim3(nb), dim3(256), 0, c->stream, c->partial, per, c->dV, dst, dstride);
+}
+
 int observe_to(chfpe_ctx *c, const double *W, double *dst) {
-  TimedScope ts(c, K_OBSERVE);
-  const int nb = std::min(kPartials, std::max(1, (int)((c->d.E + 255) / 256)));
-  hipLaunchKernelGGL((k_reduce_w0<double>), dim3(nb), dim3(256), 0, c->stream, W, c->Cw, c->wp, c->d.Q,
-                     c->d.P, c->partial);
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, c->stream, c->partial, nb, c->dV, dst);
+  observe_batch<double>(c, W, 1, dst, 1);
   return CHFPE_OK;
+}
+
+// The t2 loop of one wave: nb branch states in the batched buffers, each
+// observed after every s2 steps; Rw[j2 * B + b] receives <C> of branch b.
+template <typename T>
+int enqueue_wave(chfpe_ctx *c, int nb, long long n_t2, int s2, double dt, double *Rw) {
+  const Batch b = batch_of(c, nb);
+  const RK4Bufs<T> r{(T *)c->bb[0], (T *)c->bb[1], (T *)c->bb[2], (T *)c->bb[3], (T *)c->bb[4]};
+  for (long long j2 = 0; j2 < n_t2; ++j2) {
+    if (j2 > 0) {
+      int rc = rk4<T>(c, b, r, s2, dt);
+      if (rc) return rc;
+    }
+    observe_batch<T>(c, r.y, nb, Rw + j2 * c->d.B, 1);
+  }
+  return CHFPE_OK;
+}
+
+// Run one wave, as a captured HIP graph when possible.  The executable graph
+// is kept for the next wave of the same shape (same buffers, nb, n_t2, s2,
+// dt); without a stream of its own, or while kernel timing is on, the wave
+// is enqueued directly.
+template <typename T>
+int run_wave(chfpe_ctx *c, int nb, long long n_t2, int s2, double dt, double *Rw) {
+  if (!c->use_graphs || c->stream == nullptr || c->timing_every > 0)
+    return enqueue_wave<T>(c, nb, n_t2, s2, dt, Rw);
+  long long dtbits;
+  std::memcpy(&dtbits, &dt, sizeof dtbits);
+  const long long key[6] = {nb, n_t2, s2, dtbits, (long long)(uintptr_t)Rw, (long long)sizeof(T)};
+  if (!c->wave_graph || std::memcmp(key, c->wave_key, sizeof key) != 0) {
+    if (c->wave_graph) {
+      HIPCHK(c, hipGraphExecDestroy(c->wave_graph));
+      c->wave_graph = nullptr;
+    }
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    c->capturing = true;
+    int rc = enqueue_wave<T>(c, nb, n_t2, s2, dt, Rw);
+    c->capturing = false;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(c->stream, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(c, CHFPE_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&c->wave_graph, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      c->wave_graph = nullptr;
+      return fail(c, CHFPE_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    std::memcpy(c->wave_key, key, sizeof key);
+  }
+  HIPCHK(c, hipGraphLaunch(c->wave_graph, c->stream));
+  return CHFPE_OK;
+}
+
+// All t1 branches in waves of B: U (FP64, buffer u) is advanced along t1 one
+// branch start at a time; V_j1 = B^x U (FP64 arithmetic, stored in the branch
+// type T) fills the wave's slots; the wave then runs its t2 loop.
+template <typename T>
+int branches_batched(chfpe_ctx *c, long long n_t1, long long n_t2, int s1, int s2, double dt) {
+  const int B = c->d.B;
+  double *Rw = c->rbuf + n_t1 * n_t2;
+  long long cur = 0;
+  for (long long j0 = 0; j0 < n_t1; j0 += B) {
+    const int nb = (int)std::min<long long>(B, n_t1 - j0);
+    for (int b = 0; b < nb; ++b) {
+      const long long tgt = (j0 + b) * s1;
+      if (tgt > cur) {
+        int rc = rk4(c, c->u, tgt - cur, dt);
+        if (rc) return rc;
+        cur = tgt;
+      }
+      launch_perturb<T>(c, c->u, (T *)c->bb[0] + (size_t)b * c->d.S, c->gB);
+    }
+    int rc = run_wave<T>(c, nb, n_t2, s2, dt, Rw);
+    if (rc) return rc;
+    const int nthr = (int)(n_t2 * nb);
+    hipLaunchKernelGGL(k_scatter_r, dim3((nthr + 255) / 256), dim3(256), 0, c->stream, Rw, c->rbuf, (int)n_t2,
+                       B, nb, (int)n_t1, (int)j0);
+  }
+  return last_launch_error(c);
 }
 
 // upload grad tables (dX/dq_s on the q grid) for an optical operator
@@ -809,6 +990,7 @@ int chfpe_setup(const chfpe_params *p, void *dev_workspace, size_t ws_bytes, voi
   }
   auto at = [&](size_t off) { return c->ws + off; };
   c->F = (double *)at(L.F);
+  c->VpQ = (double *)at(L.VpQ);
   c->Vp = (double *)at(L.Vp);
   c->pm = (double *)at(L.pm);
   c->pg = (double *)at(L.pg);
@@ -828,13 +1010,24 @@ int chfpe_setup(const chfpe_params *p, void *dev_workspace, size_t ws_bytes, voi
   c->flag = (int *)at(L.flag);
   double **bp[7] = {&c->weq, &c->u, &c->y, &c->yacc, &c->xa, &c->xb, &c->t};
   for (int i = 0; i < 7; ++i) *bp[i] = (double *)at(L.bufs[i]);
+  if (d.batched)
+    for (int i = 0; i < 5; ++i) c->bb[i] = at(L.bbufs[i]);
 
   make_geom(c);
   if (const char *v = std::getenv("CHFPE_TUNE_PB_NB")) c->tune_pb_nb = std::atoi(v);
   if (const char *v = std::getenv("CHFPE_TUNE_Q_PC")) c->tune_q_pc = std::atoi(v);
+  if (const char *v = std::getenv("CHFPE_NO_GRAPH")) c->use_graphs = std::atoi(v) == 0;
   std::vector<double> F, Vp, pm, pg, sq, sp, wp, cc, tc, damp;
   std::vector<int> up, dn;
   build_tables(c, F, Vp, pm, pg, sq, sp, wp, up, dn, cc, tc, damp);
+  std::vector<double> VpQ(3 * (size_t)d.Q, 0.0);
+  for (int ql = 0; ql < d.Q; ++ql) {
+    int rem = ql;
+    for (int s = d.M - 1; s >= 0; --s) {
+      VpQ[(size_t)s * d.Q + ql] = Vp[s * kTab + rem % d.Nq[s]];
+      rem /= d.Nq[s];
+    }
+  }
   {
     double smin = 1.0;
     for (double v : sq) smin = std::min(smin, v);
@@ -851,6 +1044,7 @@ int chfpe_setup(const chfpe_params *p, void *dev_workspace, size_t ws_bytes, voi
   };
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = up_copy(c->F, F.data(), F.size() * sizeof(double));
+  if (e == hipSuccess) e = up_copy(c->VpQ, VpQ.data(), VpQ.size() * sizeof(double));
   if (e == hipSuccess) e = up_copy(c->Vp, Vp.data(), Vp.size() * sizeof(double));
   if (e == hipSuccess) e = up_copy(c->pm, pm.data(), pm.size() * sizeof(double));
   if (e == hipSuccess) e = up_copy(c->pg, pg.data(), pg.size() * sizeof(double));
@@ -869,6 +1063,7 @@ int chfpe_setup(const chfpe_params *p, void *dev_workspace, size_t ws_bytes, voi
     return fail(nullptr, CHFPE_EDEVICE, msg);
   }
   c->tb.F = c->F;
+  c->tb.VpQ = c->VpQ;
   c->tb.Vp = c->Vp;
   c->tb.pm = c->pm;
   c->tb.pg = c->pg;
@@ -896,8 +1091,8 @@ int chfpe_equilibrate(chfpe_ctx *c, int64_t n_steps, double dt) {
   {
     const int nbr = std::min(kPartials, std::max(1, (int)((c->d.E + 255) / 256)));
     hipLaunchKernelGGL((k_reduce_w0<double>), dim3(nbr), dim3(256), 0, c->stream, c->y, c->Cw, c->wp,
-                       c->d.Q, c->d.P, c->partial);
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, c->stream, c->partial, nbr, 1.0, c->scal);
+                       c->d.Q, c->d.P, c->partial, (long long)c->d.S);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, c->stream, c->partial, nbr, 1.0, c->scal, 1);
     hipLaunchKernelGGL((k_normalise<double>), dim3(1024), dim3(256), 0, c->stream, c->y, c->scal, c->dV,
                        (int)c->d.E);
   }
@@ -922,7 +1117,8 @@ int chfpe_propagate(chfpe_ctx *c, int64_t n_steps, double dt) {
 
 int chfpe_rhs(chfpe_ctx *c) {
   if (!c) return CHFPE_EINVAL;
-  launch_stage<EPI_OUT>(c, c->y, nullptr, nullptr, c->xa, 0.0);
+  const Batch b = batch_of(c, 1);
+  launch_stage<double, EPI_OUT>(c, b, c->y, c->t, nullptr, nullptr, c->xa, 0.0);
   std::swap(c->y, c->xa);
   return last_launch_error(c);
 }
@@ -933,7 +1129,7 @@ int chfpe_perturb(chfpe_ctx *c, const chfpe_optical *X) {
   std::vector<double> gt;
   grad_table(c, X, gt);
   HIPCHK(c, hipMemcpyAsync(c->gA, gt.data(), gt.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
-  launch_perturb(c, c->y, c->xa, c->gA);
+  launch_perturb<double>(c, c->y, c->xa, c->gA);
   std::swap(c->y, c->xa);
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return last_launch_error(c);
@@ -966,7 +1162,7 @@ int chfpe_response_1d(chfpe_ctx *c, const chfpe_optical *A, int64_t n_t, int32_t
   value_table(c, A, ct);
   HIPCHK(c, hipMemcpyAsync(c->gA, gt.data(), gt.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->Cw, ct.data(), ct.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
-  launch_perturb(c, c->weq, c->y, c->gA);
+  launch_perturb<double>(c, c->weq, c->y, c->gA);
   for (int64_t j = 0; j < n_t; ++j) {
     if (j > 0) {
       rc = rk4(c, c->y, stride, dt);
@@ -993,7 +1189,7 @@ int chfpe_response_2d(chfpe_ctx *c, const chfpe_optical *A, const chfpe_optical 
   if (!c->has_eq) return fail(c, CHFPE_ESTATE, "no equilibrium: call chfpe_equilibrate first");
   const int64_t n = n_t1 * n_t2;
   if (n == 0) return CHFPE_OK;
-  int rc = ensure_rbuf(c, (size_t)n);
+  int rc = ensure_rbuf(c, (size_t)(n + (c->d.batched ? (int64_t)c->d.B * n_t2 : 0)));
   if (rc) return rc;
   std::vector<double> ga, gb, ct;
   grad_table(c, A, ga);
@@ -1003,14 +1199,19 @@ int chfpe_response_2d(chfpe_ctx *c, const chfpe_optical *A, const chfpe_optical 
   HIPCHK(c, hipMemcpyAsync(c->gB, gb.data(), gb.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->Cw, ct.data(), ct.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
   // U = A^x W_eq
-  launch_perturb(c, c->weq, c->u, c->gA);
-  for (int64_t j1 = 0; j1 < n_t1; ++j1) {
+  launch_perturb<double>(c, c->weq, c->u, c->gA);
+  if (c->d.batched) {
+    rc = c->d.prec == CHFPE_FP32 ? branches_batched<float>(c, n_t1, n_t2, stride1, stride2, dt)
+                                 : branches_batched<double>(c, n_t1, n_t2, stride1, stride2, dt);
+    if (rc) return rc;
+  }
+  for (int64_t j1 = 0; j1 < (c->d.batched ? 0 : n_t1); ++j1) {
     if (j1 > 0) {
       rc = rk4(c, c->u, stride1, dt);
       if (rc) return rc;
     }
     // V = B^x U
-    launch_perturb(c, c->u, c->y, c->gB);
+    launch_perturb<double>(c, c->u, c->y, c->gB);
     for (int64_t j2 = 0; j2 < n_t2; ++j2) {
       if (j2 > 0) {
         rc = rk4(c, c->y, stride2, dt);
@@ -1134,7 +1335,7 @@ int chfpe_set_kernel_timing(chfpe_ctx *c, int32_t every) {
 }
 
 int chfpe_kernel_times(chfpe_ctx *c, int32_t max_kinds, int64_t *counts, double *mean_ms,
-                       const char **names) {
+                       double *mean_bytes, const char **names) {
   if (!c) return CHFPE_EINVAL;
   int rc = drain_timing(c);
   if (rc) return rc;
@@ -1142,29 +1343,7 @@ int chfpe_kernel_times(chfpe_ctx *c, int32_t max_kinds, int64_t *counts, double 
   for (int i = 0; i < n; ++i) {
     if (counts) counts[i] = c->kcount[i];
     if (mean_ms) mean_ms[i] = c->kcount[i] ? c->ktime[i] / c->kcount[i] : 0.0;
-    if (names) names[i] = kKindNames[i];
-  }
-  return n;
-}
-
-int chfpe_kernel_bytes(const chfpe_ctx *c, int32_t max_kinds, double *bytes, const char **names) {
-  if (!c) return CHFPE_EINVAL;
-  const double S = (double)c->d.S * sizeof(double);
-  const double E0 = (double)c->d.E * sizeof(double);
-  // each kernel's own inputs read once and outputs written once
-  const double b[kNumKinds] = {
-      2 * S,   // pblock_rhs: X -> t
-      3 * S,   // qpass_acc: X, t -> t
-      4 * S,   // s1: X(=y), t -> yacc, xa
-      6 * S,   // s2: X, t, y, yacc -> yacc, xb
-      6 * S,   // s3
-      4 * S,   // s4: X, t, yacc -> y
-      E0,      // observe: element 0
-      2 * S,   // pblock_perturb
-      3 * S};  // qpass_out: X, t -> out
-  int n = std::min<int>(max_kinds, kNumKinds);
-  for (int i = 0; i < n; ++i) {
-    if (bytes) bytes[i] = b[i];
+    if (mean_bytes) mean_bytes[i] = c->kcount[i] ? c->kbytes[i] / c->kcount[i] : 0.0;
     if (names) names[i] = kKindNames[i];
   }
   return n;
@@ -1180,6 +1359,7 @@ void chfpe_destroy(chfpe_ctx *c) {
     (void)hipEventDestroy(pd.b);
   }
   for (auto ev : c->event_pool) (void)hipEventDestroy(ev);
+  if (c->wave_graph) (void)hipGraphExecDestroy(c->wave_graph);
   if (c->rbuf) (void)hipFree(c->rbuf);
   if (c->own_ws && c->ws) (void)hipFree(c->ws);
   delete c;

@@ -97,12 +97,70 @@ __device__ __forceinline__ void compact_deriv(T (&f)[NMAX], const int N, const T
   }
 }
 
+// Same, for a line of exactly N values (no guards; N known at compile time).
+template <typename T, int N>
+__device__ __forceinline__ void compact_deriv_exact(T (&f)[N], const T ca, const T cb) {
+  constexpr T third = T(1.0 / 3.0);
+  T d[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const T fm1 = i >= 1 ? f[i >= 1 ? i - 1 : 0] : T(0);
+    const T fm2 = i >= 2 ? f[i >= 2 ? i - 2 : 0] : T(0);
+    const T fp1 = i + 1 < N ? f[i + 1 < N ? i + 1 : 0] : T(0);
+    const T fp2 = i + 2 < N ? f[i + 2 < N ? i + 2 : 0] : T(0);
+    const T r = ca * (fp1 - fm1) + cb * (fp2 - fm2);
+    d[i] = i == 0 ? r : (r - third * d[i >= 1 ? i - 1 : 0]) * T(kThomas.inv[i]);
+  }
+  f[N - 1] = d[N - 1];
+#pragma unroll
+  for (int i = N - 2; i >= 0; --i) f[i] = d[i] - T(kThomas.cp[i]) * f[i + 1];
+}
+
+// Line of N <= NMAX values; takes the unguarded path when N == NMAX.
+template <typename T, int NMAX>
+__device__ __forceinline__ void compact_line(T (&f)[NMAX], const int N, const T ca, const T cb) {
+  if (N == NMAX)
+    compact_deriv_exact<T, NMAX>(f, ca, cb);
+  else
+    compact_deriv<T, NMAX>(f, N, ca, cb);
+}
+
+// Same derivative for a line of N values held in LDS at base + i * stride,
+// in place, with O(1) registers: a five-value window of the input moves
+// ahead of the forward sweep, which stores d_i over f_i once f_i is in the
+// window; the backward sweep then overwrites d_i with the result.
+template <typename T>
+__device__ __forceinline__ void compact_lds(T *G, const int base, const int stride, const int N, const T ca,
+                                            const T cb) {
+  constexpr T third = T(1.0 / 3.0);
+  T fm2 = T(0), fm1 = T(0), f0 = G[base], fp1 = N > 1 ? G[base + stride] : T(0);
+  T fp2 = N > 2 ? G[base + 2 * stride] : T(0);
+  T dprev = T(0);
+  for (int i = 0; i < N; ++i) {
+    const T r = ca * (fp1 - fm1) + cb * (fp2 - fm2);
+    const T d = i == 0 ? r : (r - third * dprev) * T(kThomas.inv[i]);
+    G[base + i * stride] = d;
+    dprev = d;
+    fm2 = fm1;
+    fm1 = f0;
+    f0 = fp1;
+    fp1 = fp2;
+    fp2 = (i + 3 < N) ? G[base + (i + 3) * stride] : T(0);
+  }
+  T y = dprev;
+  for (int i = N - 2; i >= 0; --i) {
+    y = G[base + i * stride] - T(kThomas.cp[i]) * y;
+    G[base + i * stride] = y;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Geometry and tables passed by value to every kernel.
 // ---------------------------------------------------------------------------
 struct Geom {
   int M;         // modes
   int ne;        // hierarchy elements
+  int nbatch;    // independent states (t1 branches) stored back to back
   int Nq[3], Np[3];
   int Q;         // prod Nq
   int P;         // prod Np (one p-block)
@@ -117,6 +175,7 @@ struct Geom {
 
 struct Tabs {
   const double *F;      // [s][qlin]  dU/dq_s
+  const double *VpQ;    // [s][qlin]  V_s'(q_s) on the q grid
   const double *Vp;     // [s][j]     V_s'(q_s,j)          (stride kTab)
   const double *pm;     // [s][j]     p_s,j / m_s          (stride kTab)
   const double *pg;     // [s][j]     p_s,j                (stride kTab)
@@ -196,78 +255,138 @@ struct QPass {
 // Three phases: (1) one pass over the run loads h_n and its neighbours once,
 // keeps the pointwise terms in registers and writes both derivative fields to
 // LDS; (2) row and column lines are solved together; (3) one pass writes out.
-template <typename T, int NMAX, int RPT, bool PERTURB>
+// T: type of X and of the arithmetic; TO: type of out.  A batch of nbatch
+// states is laid out [branch][n][q][p]; tasks cover every (branch, n).
+template <typename T, typename TO, int NMAX, int RPT, int MM, bool PERTURB>
 __global__ void __launch_bounds__(256)
-k_pblock(const Geom g, const Tabs tb, const PBlock pb, const T *__restrict__ X, T *__restrict__ out,
+k_pblock(const Geom g, const Tabs tb, const PBlock pb, const T *__restrict__ X, TO *__restrict__ out,
          const double *__restrict__ grad) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *Ga = reinterpret_cast<T *>(smem_raw);  // row axis p_M
-  T *Gb = Ga + pb.tileP;                    // column axis p_{M-1} (NB == 2)
+  T *Gb = Ga + pb.tileP;                    // column axis p_{M-1} (two or three modes)
   const int task = xcd_task(blockIdx.x, pb.nblk);
   if (task >= pb.ntasks) return;
-  const int e = task % g.ne;
-  const int b0 = (task / g.ne) * pb.nb;
+  constexpr int NB = MM == 1 ? 1 : 2;
+  constexpr int sa = MM - 1;  // row axis
+  constexpr int sb = MM - 2;  // column axis (NB == 2)
+  const int ne_all = g.ne * g.nbatch;
+  const int ea = task % ne_all;   // (branch, element)
+  const int br = ea / g.ne;
+  const int e = ea - br * g.ne;
+  const int b0 = (task / ne_all) * pb.nb;
   const int nbt = min(pb.nb, pb.nblocks - b0);
-  const int M = g.M;
   const int rows = pb.rows, cols = pb.cols, cp = pb.cols + 1;
   const int nrows = nbt * rows;
-  const long long E = g.E;
-  const long long eoff = (long long)e * E;
   const int tid = threadIdx.x;
   const int col = tid % cols;
-  const int rg = tid / cols;
-  const bool owner = rg < pb.RG;
-  const int sa = M - 1;               // row axis
-  const int sb = M - 2;               // column axis (NB == 2)
-  const int so = M - 3;               // outer p axis inside the p-block (three modes)
+  const int rg = min(tid / cols, pb.RG - 1);  // surplus threads duplicate the last group's work
+  const bool owner = tid < pb.RG * cols;
+  const int Q = g.Q;
 
-  int up[3], dn[3];
-  double cc[3], tc[3];
+  // base pointers of the run in this element and its neighbours; a missing
+  // neighbour points at the element itself and gets a zero factor, so every
+  // load below is unconditional
+  const long long run0 = (long long)b0 * pb.B;
+  const T *Xe = X + (long long)ea * g.E + run0;
+  TO *Oe = out + (long long)ea * g.E + run0;
+  const T *Xb = X + (long long)br * g.ne * g.E;  // this branch's element 0
+  const T *Xu[MM];
+  const T *Xd[MM];
+  double fu[MM], cc[MM], tcv[MM];
 #pragma unroll
-  for (int s = 0; s < 3; ++s) {
-    up[s] = (!PERTURB && s < M) ? tb.up[e * 3 + s] : -1;
-    dn[s] = (!PERTURB && s < M) ? tb.dn[e * 3 + s] : -1;
-    cc[s] = (!PERTURB && s < M) ? tb.cc[e * 3 + s] : 0.0;
-    tc[s] = (!PERTURB && s < M) ? tb.tc[e * 3 + s] : 0.0;
+  for (int s = 0; s < MM; ++s) {
+    const int up = PERTURB ? -1 : tb.up[e * 3 + s];
+    const int dn = PERTURB ? -1 : tb.dn[e * 3 + s];
+    Xu[s] = up >= 0 ? Xb + (long long)up * g.E + run0 : Xe;
+    Xd[s] = dn >= 0 ? Xb + (long long)dn * g.E + run0 : Xe;
+    fu[s] = up >= 0 ? 1.0 : 0.0;
+    cc[s] = PERTURB ? 0.0 : tb.cc[e * 3 + s];        // zero when n_s = 0
+    tcv[s] = PERTURB ? 0.0 : 0.5 * tb.tc[e * 3 + s];  // zero when n_s = 0
   }
-  const T dmp = PERTURB ? T(0) : T(tb.damp[e]);
+  const double dmp = PERTURB ? 0.0 : tb.damp[e];
   const double p_col = tb.pg[sa * kTab + col];
 
-  // ---- phase 1 ----------------------------------------------------------------
-  T pw[RPT];
+  // ---- phase 1: rows R_k = rg + k RG of the run --------------------------------
+  // Row R = k RG + rg.  For two or three modes the host picks RG | rows, so
+  // the block of batch k, (k RG) / rows, is the same for the whole workgroup.
+  int off[RPT], qlk[RPT], rk[RPT], jok[RPT];
+  {
+    int blk = 0, r = rg;
+    while (r >= rows) {
+      r -= rows;
+      ++blk;
+    }
 #pragma unroll
-  for (int k = 0; k < RPT; ++k) {
-    pw[k] = T(0);
-    const int R = rg + k * pb.RG;
-    if (!owner || R >= nrows) continue;
-    const int blk = R / rows;
-    const int r = R - blk * rows;
-    const int ob = b0 + blk;
-    const int ql = ob / pb.bpq;
-    const int jo = ob - ql * pb.bpq;       // outer p index inside the p-block
-    const int rel = ob * pb.B + r * cols + col;
-    const int li = R * cp + col;
-    const T h = X[eoff + rel];
-    // p coordinates of this point on every axis
-    double ps[3];
-    ps[sa] = p_col;
-    if (pb.NB == 2) ps[sb] = tb.pg[sb * kTab + r];
-    if (M == 3) ps[so] = tb.pg[so * kTab + jo];
-    if (PERTURB) {
+    for (int k = 0; k < RPT; ++k) {
+      const int R = rg + k * pb.RG;
+      const bool valid = R < nrows;
+      int bl, rr;
+      if (NB == 2) {
+        bl = valid ? (k * pb.RG) / rows : 0;  // uniform; rows past the run re-read block 0
+        rr = valid ? (k * pb.RG) % rows + rg : rg;
+      } else {
+        bl = valid ? blk : 0;
+        rr = 0;
+      }
+      const int ob = b0 + bl;
+      qlk[k] = ob / pb.bpq;
+      jok[k] = ob - qlk[k] * pb.bpq;
+      rk[k] = rr;
+      off[k] = bl * pb.B + rr * cols + col;
+      r += pb.RG;
+      while (r >= rows) {
+        r -= rows;
+        ++blk;
+      }
+    }
+  }
+  T hv[RPT];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) hv[k] = Xe[off[k]];
+  T pw[RPT];
+  if (PERTURB) {
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int ql = qlk[k];
+      double ps[MM];
+      ps[sa] = p_col;
+      if (NB == 2) ps[sb] = tb.pg[sb * kTab + rk[k]];
+      if (MM == 3) ps[0] = tb.pg[0 * kTab + jok[k]];
       double c = 0.0;
-      for (int s = 0; s < M; ++s) c += grad[(long long)s * g.Q + ql] * g.bm[s] * ps[s];
+#pragma unroll
+      for (int s = 0; s < MM; ++s) c += grad[s * Q + ql] * g.bm[s] * ps[s];
+      const T h = hv[k];
       pw[k] = -T(c) * h;
-      Ga[li] = T(grad[(long long)sa * g.Q + ql]) * h;
-      if (pb.NB == 2) Gb[li] = T(grad[(long long)sb * g.Q + ql]) * h;
-    } else {
-      T acc = -dmp * h;
-      for (int s = 0; s < M; ++s) {
-        const T hu = up[s] >= 0 ? X[(long long)up[s] * E + rel] : T(0);
-        const T hd = dn[s] >= 0 ? X[(long long)dn[s] * E + rel] : T(0);
-        const double vp = tb.Vp[s * kTab + (ql / g.QS[s]) % g.Nq[s]];
-        acc += T(vp * ps[s] * 0.5 * tc[s]) * hd - T(vp * ps[s] * g.bm[s]) * hu;
-        if (s == sa || (pb.NB == 2 && s == sb)) {
-          const T G = T(tb.F[(long long)s * g.Q + ql]) * h + T(vp) * (hu + T(cc[s]) * hd);
+      const int li = (rg + k * pb.RG) * cp + col;
+      Ga[li] = T(grad[sa * Q + ql]) * h;
+      if (NB == 2) Gb[li] = T(grad[sb * Q + ql]) * h;
+    }
+  } else {
+    T hu[MM][RPT], hd[MM][RPT];
+#pragma unroll
+    for (int s = 0; s < MM; ++s)
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        hu[s][k] = Xu[s][off[k]];
+        hd[s][k] = Xd[s][off[k]];
+      }
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int ql = qlk[k];
+      double ps[MM];
+      ps[sa] = p_col;
+      if (NB == 2) ps[sb] = tb.pg[sb * kTab + rk[k]];
+      if (MM == 3) ps[0] = tb.pg[0 * kTab + jok[k]];
+      const T h = hv[k];
+      T acc = -T(dmp) * h;
+      const int li = (rg + k * pb.RG) * cp + col;
+#pragma unroll
+      for (int s = 0; s < MM; ++s) {
+        const double vp = tb.VpQ[s * Q + ql];
+        const T u = T(fu[s]) * hu[s][k];
+        acc += T(vp * ps[s] * tcv[s]) * hd[s][k] - T(vp * ps[s] * g.bm[s]) * u;
+        if (s == sa || (NB == 2 && s == sb)) {
+          const T G = T(tb.F[s * Q + ql]) * h + T(vp) * (u + T(cc[s]) * hd[s][k]);
           if (s == sa)
             Ga[li] = G;
           else
@@ -282,7 +401,7 @@ k_pblock(const Geom g, const Tabs tb, const PBlock pb, const T *__restrict__ X, 
   // ---- phase 2: rows of Ga and columns of Gb ------------------------------------
   {
     const int nla = nrows;
-    const int nlb = pb.NB == 2 ? nbt * cols : 0;
+    const int nlb = NB == 2 ? nbt * cols : 0;
     for (int l = tid; l < nla + nlb; l += blockDim.x) {
       T *G;
       int base, stride, N;
@@ -302,16 +421,19 @@ k_pblock(const Geom g, const Tabs tb, const PBlock pb, const T *__restrict__ X, 
         base = blk * rows * cp + c;
         stride = cp;
         N = rows;
-        ca = T(g.dp_ca[sb]);
-        cb = T(g.dp_cb[sb]);
+        ca = T(g.dp_ca[NB == 2 ? sb : sa]);
+        cb = T(g.dp_cb[NB == 2 ? sb : sa]);
       }
-      T f[NMAX];
+      if (N == NMAX) {
+        T f[NMAX];
 #pragma unroll
-      for (int i = 0; i < NMAX; ++i) f[i] = (i < N) ? G[base + i * stride] : T(0);
-      compact_deriv<T, NMAX>(f, N, ca, cb);
+        for (int i = 0; i < NMAX; ++i) f[i] = G[base + i * stride];
+        compact_deriv_exact<T, NMAX>(f, ca, cb);
 #pragma unroll
-      for (int i = 0; i < NMAX; ++i)
-        if (i < N) G[base + i * stride] = f[i];
+        for (int i = 0; i < NMAX; ++i) G[base + i * stride] = f[i];
+      } else {
+        compact_lds<T>(G, base, stride, N, ca, cb);
+      }
     }
   }
   __syncthreads();
@@ -320,14 +442,10 @@ k_pblock(const Geom g, const Tabs tb, const PBlock pb, const T *__restrict__ X, 
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
     const int R = rg + k * pb.RG;
-    if (!owner || R >= nrows) continue;
-    const int blk = R / rows;
-    const int r = R - blk * rows;
-    const int rel = (b0 + blk) * pb.B + r * cols + col;
     const int li = R * cp + col;
     T v = pw[k] + Ga[li];
-    if (pb.NB == 2) v += Gb[li];
-    out[eoff + rel] = v;
+    if (NB == 2) v += Gb[li];
+    if (owner && R < nrows) Oe[off[k]] = TO(v);
   }
 }
 
@@ -350,8 +468,9 @@ __device__ __forceinline__ void split_pos(const Geom &g, const int rel, int &ql,
 }
 
 // value of the field of mode s at relative position rel of element e
+// Xb: element 0 of the branch; e: element within the branch
 template <typename T, int FIELD>
-__device__ __forceinline__ T field_at(const Geom &g, const Tabs &tb, const T *__restrict__ X,
+__device__ __forceinline__ T field_at(const Geom &g, const Tabs &tb, const T *__restrict__ Xb,
                                       const double *__restrict__ grad, const int e, const int s,
                                       const int rel, const T w) {
   if (FIELD == FQ) return w;
@@ -362,15 +481,16 @@ __device__ __forceinline__ T field_at(const Geom &g, const Tabs &tb, const T *__
   const int dn = tb.dn[e * 3 + s];
   const double vp = tb.Vp[s * kTab + (ql / g.QS[s]) % g.Nq[s]];
   T Gv = T(tb.F[(long long)s * g.Q + ql]) * w;
-  if (up >= 0) Gv += T(vp) * X[(long long)up * g.E + rel];
-  if (dn >= 0) Gv += T(vp * tb.cc[e * 3 + s]) * X[(long long)dn * g.E + rel];
+  if (up >= 0) Gv += T(vp) * Xb[(long long)up * g.E + rel];
+  if (dn >= 0) Gv += T(vp * tb.cc[e * 3 + s]) * Xb[(long long)dn * g.E + rel];
   return Gv;
 }
 
-template <typename T, int NMAX, bool TWO, int EPI, int FA, int FB>
+// T: type of X and of the arithmetic; TO: type of Tacc, y, yacc, xo.
+template <typename T, typename TO, int NMAX, bool TWO, int EPI, int FA, int FB>
 __global__ void __launch_bounds__(512)
-k_qpass(const Geom g, const Tabs tb, const QPass qp, const T *__restrict__ X, T *__restrict__ Tacc,
-        const T *__restrict__ y, T *__restrict__ yacc, T *__restrict__ xo, const double *__restrict__ grad,
+k_qpass(const Geom g, const Tabs tb, const QPass qp, const T *__restrict__ X, TO *__restrict__ Tacc,
+        const TO *__restrict__ y, TO *__restrict__ yacc, TO *__restrict__ xo, const double *__restrict__ grad,
         const double dt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *lds = reinterpret_cast<T *>(smem_raw);
@@ -379,7 +499,9 @@ k_qpass(const Geom g, const Tabs tb, const QPass qp, const T *__restrict__ X, T 
   const int chunk = task % qp.nchunk;
   const int t2 = task / qp.nchunk;
   const int rest = t2 % qp.nrest;
-  const int e = t2 / qp.nrest;
+  const int ea = t2 / qp.nrest;  // (branch, element)
+  const int br = ea / g.ne;
+  const int e = ea - br * g.ne;
   const int p0 = chunk * qp.pc;
   const int pcn = min(qp.pc, qp.run - p0);
   int rel = p0;
@@ -397,21 +519,25 @@ k_qpass(const Geom g, const Tabs tb, const QPass qp, const T *__restrict__ X, T 
   const int Na = qp.Na;
   const bool active = (c < pcn) && (jb < (TWO ? qp.Nb : 1));
   const int lrel = rel + (TWO ? jb * qp.sb : 0) + c;  // line start within the element
-  const long long ebase = (long long)e * g.E;
+  const long long ebase = (long long)ea * g.E;
+  const T *Xb = X + (long long)br * g.ne * g.E;
 
   T f[NMAX];
 #pragma unroll
   for (int i = 0; i < NMAX; ++i)
     f[i] = (active && i < Na) ? X[ebase + lrel + i * qp.sa] : T(0);
 
+  // LDS tile [ja][jb][c] with row stride (Nb + 1) * pc: the pad keeps the
+  // b-line reads of different ja in different banks
+  const int rs = (qp.Nb + 1) * qp.pc;
   if (TWO) {
     const int Nb = qp.Nb, pc = qp.pc;
     if (active) {
 #pragma unroll
       for (int i = 0; i < NMAX; ++i)
         if (i < Na) {
-          lds[(i * Nb + jb) * pc + c] =
-              field_at<T, FB>(g, tb, X, grad, e, qp.sb_mode, lrel + i * qp.sa, f[i]);
+          lds[i * rs + jb * pc + c] =
+              field_at<T, FB>(g, tb, Xb, grad, e, qp.sb_mode, lrel + i * qp.sa, f[i]);
         }
     }
     __syncthreads();
@@ -419,11 +545,11 @@ k_qpass(const Geom g, const Tabs tb, const QPass qp, const T *__restrict__ X, T 
     if (c < pcn && ja < Na) {
       T h[NMAX];
 #pragma unroll
-      for (int i = 0; i < NMAX; ++i) h[i] = (i < Nb) ? lds[(ja * Nb + i) * pc + c] : T(0);
-      compact_deriv<T, NMAX>(h, Nb, T(qp.ca_b), T(qp.cb_b));
+      for (int i = 0; i < NMAX; ++i) h[i] = (i < Nb) ? lds[ja * rs + i * pc + c] : T(0);
+      compact_line<T, NMAX>(h, Nb, T(qp.ca_b), T(qp.cb_b));
 #pragma unroll
       for (int i = 0; i < NMAX; ++i)
-        if (i < Nb) lds[(ja * Nb + i) * pc + c] = h[i];
+        if (i < Nb) lds[ja * rs + i * pc + c] = h[i];
     }
     __syncthreads();
   }
@@ -436,9 +562,9 @@ k_qpass(const Geom g, const Tabs tb, const QPass qp, const T *__restrict__ X, T 
     if (FA == FQ)
       d[i] = f[i];
     else
-      d[i] = (i < Na) ? field_at<T, FA>(g, tb, X, grad, e, qp.sa_mode, lrel + i * qp.sa, f[i]) : T(0);
+      d[i] = (i < Na) ? field_at<T, FA>(g, tb, Xb, grad, e, qp.sa_mode, lrel + i * qp.sa, f[i]) : T(0);
   }
-  compact_deriv<T, NMAX>(d, Na, T(qp.ca_a), T(qp.cb_a));
+  compact_line<T, NMAX>(d, Na, T(qp.ca_a), T(qp.cb_a));
 
   // coefficients: -p_s/m_s for q-type axes (p_s is fixed along the line)
   int ql0, pix0;
@@ -457,27 +583,27 @@ k_qpass(const Geom g, const Tabs tb, const QPass qp, const T *__restrict__ X, T 
   for (int i = 0; i < NMAX; ++i) {
     if (i < Na) {
       T kv = ka * d[i];
-      if (TWO) kv += kb * lds[(i * qp.Nb + jb) * qp.pc + c];
+      if (TWO) kv += kb * lds[i * rs + jb * qp.pc + c];
       const long long idx = ebase + lrel + i * qp.sa;
       if (EPI == EPI_ACC) {
-        Tacc[idx] += kv;
+        Tacc[idx] = TO(T(Tacc[idx]) + kv);
       } else {
-        kv += Tacc[idx];
+        kv += T(Tacc[idx]);
         if (EPI == EPI_OUT) {
-          xo[idx] = kv;
+          xo[idx] = TO(kv);
         } else if (EPI == EPI_S1) {
-          yacc[idx] = f[i] + h6 * kv;
-          xo[idx] = f[i] + h2 * kv;
+          yacc[idx] = TO(f[i] + h6 * kv);
+          xo[idx] = TO(f[i] + h2 * kv);
         } else if (EPI == EPI_S2) {
-          const T yv = y[idx];
-          yacc[idx] += h3 * kv;
-          xo[idx] = yv + h2 * kv;
+          const T yv = T(y[idx]);
+          yacc[idx] = TO(T(yacc[idx]) + h3 * kv);
+          xo[idx] = TO(yv + h2 * kv);
         } else if (EPI == EPI_S3) {
-          const T yv = y[idx];
-          yacc[idx] += h3 * kv;
-          xo[idx] = yv + h1 * kv;
+          const T yv = T(y[idx]);
+          yacc[idx] = TO(T(yacc[idx]) + h3 * kv);
+          xo[idx] = TO(yv + h1 * kv);
         } else {  // EPI_S4
-          xo[idx] = yacc[idx] + h6 * kv;
+          xo[idx] = TO(T(yacc[idx]) + h6 * kv);
         }
       }
     }
@@ -493,13 +619,16 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// partial[block] = sum over this block's share of element 0 of
-// Cw[qlin] * wp[pidx] * W[qlin * P + pidx]   (fixed order for a fixed grid)
+// partial[branch][block] = sum over this block's share of element 0 of
+// Cw[qlin] * wp[pidx] * W[qlin * P + pidx]   (fixed order for a fixed grid);
+// blockIdx.y selects the branch, whose state starts at W + branch * bstride.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_reduce_w0(const T *__restrict__ W, const double *__restrict__ Cw, const double *__restrict__ wp,
-            const int Q, const int P, double *__restrict__ partial) {
+            const int Q, const int P, double *__restrict__ partial, const long long bstride) {
   __shared__ double sh[4];
+  W += (long long)blockIdx.y * bstride;
+  partial += (long long)blockIdx.y * gridDim.x;
   double s = 0.0;
   const int n = Q * P;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
@@ -513,11 +642,13 @@ k_reduce_w0(const T *__restrict__ W, const double *__restrict__ Cw, const double
   if (threadIdx.x == 0) partial[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 
-// out[0] = scale * sum(partial[0..n)), summed in a fixed order by one block.
+// out[b * ostride] = scale * sum(partial[b][0..n)), fixed order, one block per branch b.
 __global__ void __launch_bounds__(256)
 k_reduce_final(const double *__restrict__ partial, const int n, const double scale,
-               double *__restrict__ out) {
+               double *__restrict__ out, const int ostride) {
   __shared__ double sh[4];
+  partial += (long long)blockIdx.x * n;
+  out += (long long)blockIdx.x * ostride;
   double s = 0.0;
   for (int i = threadIdx.x; i < n; i += 256) s += partial[i];
   s = wave_sum(s);
@@ -623,6 +754,17 @@ k_spectrum_out(const double2 *__restrict__ z, const long long n, const int n_fas
   if (i >= n) return;
   const double w = with_omega ? dw * (double)(i % n_fast) : 1.0;
   I[i] = scale * w * z[i].y;
+}
+
+// R[j2 * n_t1 + j0 + b] = Rw[j2 * B + b] for b < nb
+__global__ void __launch_bounds__(256)
+k_scatter_r(const double *__restrict__ Rw, double *__restrict__ R, const int n_t2, const int B, const int nb,
+            const int n_t1, const int j0) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n_t2 * nb) return;
+  const int j2 = i / nb;
+  const int b = i - j2 * nb;
+  R[(long long)j2 * n_t1 + j0 + b] = Rw[(long long)j2 * B + b];
 }
 
 // dst = src, 16-byte vectors

@@ -200,3 +200,79 @@ def test_spectra_parity(pk):
     R3 = rng.standard_normal((7, 5))  # ragged, odd sizes
     _, _, I3_ref = orc.spectrum_2d(R3, 0.3, 0.1)
     assert rel_l2(pk.spectrum_2d(R3, 0.3, 0.1), I3_ref) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# batched t1 branches (waves of B states), HIP graphs, FP32 branch states
+# ---------------------------------------------------------------------------
+
+def _ops(M):
+    A = wl.workload("three_mode_24")["A"]
+    B = wl.workload("three_mode_24")["B"]
+    A = {"lin": A["lin"][:M], "quad": [r[:M] for r in A["quad"][:M]]}
+    B = {"lin": B["lin"][:M], "quad": [r[:M] for r in B["quad"][:M]]}
+    return A, B
+
+
+@pytest.mark.parametrize("name", ["m2_n10_k2", "m3_n8_k2"])
+def test_response_2d_batched_fp64_parity(pk, name):
+    """Seven t1 branches in waves of 3, 3 and 1 (graph replays with eager
+    work in between, a smaller last wave), FP64, against the oracle."""
+    w = SMALL[name]
+    A, B = _ops(w["M"])
+    say(f"[batched fp64] {name}")
+    Weq = orc.equilibrate(w, 10, 0.004)
+    ref = orc.response_2d(w, A, B, A, Weq, 7, 5, 2, 3, 0.004)
+    with pk.Solver(pk.params_from_workload(w, precision=pk.CHFPE_FP64, batch=3)) as s:
+        s.equilibrate(10, 0.004)
+        got = s.response_2d(A, B, A, 7, 5, 2, 3, 0.004)
+        again = s.response_2d(A, B, A, 7, 5, 2, 3, 0.004)  # cached graph, second use
+    assert rel_l2(got, ref) < FP64_TOL
+    assert np.array_equal(got, again)
+
+
+def test_graph_and_eager_waves_agree(pk, monkeypatch):
+    """The captured wave graph and the same launches issued directly give
+    identical results (deterministic kernels, fixed-order reductions)."""
+    w = SMALL["m2_n12_k3"]
+    A, B = _ops(2)
+    say("[graph vs eager]")
+    out = []
+    for flag in ("0", "1"):
+        monkeypatch.setenv("CHFPE_NO_GRAPH", flag)
+        with pk.Solver(pk.params_from_workload(w, precision=pk.CHFPE_FP64, batch=4)) as s:
+            s.equilibrate(5, 0.004)
+            out.append(s.response_2d(A, B, A, 9, 6, 1, 2, 0.004))
+    assert np.array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("name", ["m2_n12_k3", "m3_n8_k2"])
+def test_response_2d_fp32_branches(pk, name):
+    """FP32 branch states (FP64 equilibrium, t1 trajectory, excitations and
+    reductions) against the FP64 oracle: relative L2 <= 1e-4."""
+    w = SMALL[name]
+    A, B = _ops(w["M"])
+    say(f"[fp32 branches] {name}")
+    Weq = orc.equilibrate(w, 10, 0.004)
+    ref = orc.response_2d(w, A, B, A, Weq, 6, 8, 2, 2, 0.004)
+    with pk.Solver(pk.params_from_workload(w, precision=pk.CHFPE_FP32, batch=4)) as s:
+        s.equilibrate(10, 0.004)
+        got = s.response_2d(A, B, A, 6, 8, 2, 2, 0.004)
+    err = rel_l2(got, ref)
+    say(f"    fp32 rel L2 = {err:.2e}")
+    assert err < 1e-4
+
+
+@pytest.mark.parametrize("kind", ["RTT", "TRT", "TTR"])
+def test_response_2d_orderings_and_resolved_stride(pk, kind):
+    """The three THz-Raman orderings (operator swaps through the same entry
+    point) with a physically resolved stride of 8 RK4 steps per sample."""
+    w = SMALL["m2_n12_k3"]
+    A, B, C = wl.response_types(w)[kind]
+    say(f"[ordering] {kind}")
+    Weq = orc.equilibrate(w, 10, 0.004)
+    ref = orc.response_2d(w, A, B, C, Weq, 4, 5, 8, 8, 0.004)
+    with solver(pk, w) as s:
+        s.equilibrate(10, 0.004)
+        got = s.response_2d(A, B, C, 4, 5, 8, 8, 0.004)
+    assert rel_l2(got, ref) < FP64_TOL

@@ -180,3 +180,12 @@ def draw_perturbed(w: dict, seed: int, rel: float = 0.2) -> dict:
         out[key] = [[x * rng.uniform(1 - rel, 1 + rel) for x in row] for row in out[key]]
     out["beta"] = out["beta"] * rng.uniform(1 - rel, 1 + rel)
     return out
+
+
+def response_types(w: dict) -> dict:
+    """Operator triples (A, B, C) of the three 2D THz-Raman orderings of
+    Sec. V: Raman-THz-THz (A = Pi), THz-Raman-THz (B = Pi), THz-THz-Raman
+    (C = Pi); the other operators are the dipole mu."""
+    M = int(w["M"])
+    mu, pi = _dipole(M), _polarizability(M)
+    return {"RTT": (pi, mu, mu), "TRT": (mu, pi, mu), "TTR": (mu, mu, pi)}
