@@ -85,6 +85,194 @@ def cpu_baseline(w, pk, target_s: float, sample_note: str):
     }, err, n + 1
 
 
+
+# ---------------------------------------------------------------------------
+# rocprofv3 output -> text summaries under profiles/ (runs without a GPU)
+
+_EPI_KIND = {0: "qpass_acc", 1: "qpass_out", 2: "qpass_rk4_s1", 3: "qpass_rk4_s2",
+             4: "qpass_rk4_s3", 5: "qpass_rk4_s4"}
+
+
+def _short_name(name: str) -> str:
+    s = name.split("(")[0] if not name.startswith("void ") else name[5:].split("(")[0]
+    return s.replace("chfpe::", "").strip()
+
+
+def _kind_of(short: str, grid: int, min_grid: dict):
+    """Library kernel kind of one dispatch (the names chfpe_kernel_times uses);
+    a launch over several branch states has a larger grid than the single-state
+    launch of the same instantiation, and FP32 launches are always batched."""
+    fam = short.split("<")[0]
+    targs = [a.strip() for a in short[short.find("<") + 1:short.rfind(">")].split(",")] if "<" in short else []
+    if fam == "k_pblock":
+        kind = "perturb" if targs[-1] == "true" else "pblock_rhs"
+    elif fam == "k_qpass":
+        if int(targs[5]) == 2:        # dX/dq field: second launch of a perturbation
+            kind = "perturb_q"
+        else:
+            kind = _EPI_KIND[int(targs[4])]
+    elif fam == "k_reduce_w0":
+        kind = "observe"
+    else:
+        return None
+    batched = (targs and targs[0] == "float" and kind != "perturb") or grid > min_grid.get(short, grid)
+    return ("batch_" + kind) if batched else kind
+
+
+def _grid(row: dict) -> int:
+    if "Grid_Size" in row:
+        return int(float(row["Grid_Size"]))
+    g = 1
+    for ax in ("X", "Y", "Z"):
+        g *= int(float(row.get(f"Grid_Size_{ax}", 1) or 1))
+    return g
+
+
+def _csv(folder: str, suffix: str):
+    import csv
+    import glob
+    files = sorted(glob.glob(os.path.join(folder, "**", f"*{suffix}"), recursive=True))
+    if not files:
+        raise SystemExit(f"no *{suffix} under {folder}")
+    with open(files[0], newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def _cmd(args, extra: str) -> str:
+    return (f"python bench.py {extra} --workload {args.workload} --batch {args.batch} "
+            f"--precision {args.precision}" + (f" --tiles {args.tiles}" if args.tiles else ""))
+
+
+def summarise(args) -> int:
+    tag = f"{args.workload}_{args.precision}_b{args.batch}"
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    bench_cmd = _cmd(args, "--steps 1 --warmup 0 --no-cpu-baseline")
+    kern_cmd = _cmd(args, "--mode kernels --rk4-steps 4")
+    if args.trace_dir:
+        rows = _csv(args.trace_dir, "kernel_trace.csv")
+        rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+        marks = [i for i, r in enumerate(rows) if "k_stream_copy" in r["Kernel_Name"]]
+        if marks:  # the timed region of bench.py starts after its marker copy
+            rows = rows[marks[-1] + 1:]
+        min_grid = {}
+        for r in rows:
+            s = _short_name(r["Kernel_Name"])
+            min_grid[s] = min(min_grid.get(s, 1 << 62), _grid(r))
+        groups = {}
+        for r in rows:
+            s = _short_name(r["Kernel_Name"])
+            g = _grid(r)
+            d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6
+            e = groups.setdefault((s, g), [0, 0.0, _kind_of(s, g, min_grid)])
+            e[0] += 1
+            e[1] += d
+        total = sum(e[1] for e in groups.values())
+        ev = {}
+        if args.bench_json and os.path.exists(args.bench_json):
+            for line in open(args.bench_json):
+                if line.startswith("{"):
+                    ev = json.loads(line).get("kernel_mean_ms", {})
+        lines = [f"# Kernel trace: {args.workload}, {args.precision} branch states, "
+                 f"{args.batch}-branch waves, one bench step",
+                 "", "Command (repository root, ROCm 7 rocprofv3):", "",
+                 f"    rocprofv3 --kernel-trace --stats --output-format csv -d <out> -o run -- {bench_cmd}",
+                 "", "Per kernel instantiation and grid, from the kernel trace of the timed region "
+                 "(dispatches after bench.py's marker copy; durations from the trace's timestamps; "
+                 "`event mean` is the same run's HIP-event mean of that kind, from the JSON line "
+                 "bench.py printed):", "",
+                 "| kind | kernel | grid | calls | mean ms | event mean ms | total s | share |",
+                 "|---|---|---|---|---|---|---|---|"]
+        for (s, g), (n, t, kind) in sorted(groups.items(), key=lambda kv: -kv[1][1])[:24]:
+            em = ev.get(kind) if kind else None
+            lines.append(f"| {kind or '-'} | `{s[:70]}` | {g} | {n} | {t / n:.4f} | "
+                         f"{'%.4f' % em if em else '-'} | {t / 1e3:.3f} | {100 * t / total:.1f}% |")
+        st = _csv(args.trace_dir, "kernel_stats.csv")
+        lines += ["", "rocprofv3 --stats (kernel_stats.csv, the whole run: setup, autotuning, warmup "
+                  "and the timed step), top 12 by total time:", "",
+                  "| kernel | calls | total s | mean ms | % |", "|---|---|---|---|---|"]
+        for r in st[:12]:
+            lines.append(f"| `{_short_name(r['Name'])[:70]}` | {r['Calls']} | "
+                         f"{float(r['TotalDurationNs']) * 1e-9:.3f} | {float(r['AverageNs']) * 1e-6:.4f} | "
+                         f"{float(r['Percentage']):.1f} |")
+        path = os.path.join(ROOT, "profiles", f"kernel_trace_{tag}.md")
+        open(path, "w").write("\n".join(lines) + "\n")
+        log(f"[summarise] wrote {path}")
+    if args.fetch_dir and args.write_dir:
+        per = {}
+        for which, folder in (("fetch", args.fetch_dir), ("write", args.write_dir)):
+            rows = _csv(folder, "counter_collection.csv")
+            min_grid = {}
+            for r in rows:
+                s = _short_name(r["Kernel_Name"])
+                min_grid[s] = min(min_grid.get(s, 1 << 62), _grid(r))
+            for r in rows:
+                s = _short_name(r["Kernel_Name"])
+                kind = "copy" if s.startswith("k_stream_copy") else _kind_of(s, _grid(r), min_grid)
+                if kind is None:
+                    continue
+                e = per.setdefault(kind, {}).setdefault(which, [0, 0.0])
+                e[0] += 1
+                e[1] += float(r["Counter_Value"]) * 1024.0
+        kj = {}
+        if args.kernels_json and os.path.exists(args.kernels_json):
+            for line in open(args.kernels_json):
+                if line.startswith("{"):
+                    kj = json.loads(line)
+        copy_bytes = float(kj.get("copy_bytes", 1 << 30))
+        ff = copy_bytes / (per["copy"]["fetch"][1] / per["copy"]["fetch"][0])
+        wf = copy_bytes / (per["copy"]["write"][1] / per["copy"]["write"][0])
+        alg = kj.get("kernel_bytes", {})
+        rec = {"workload": args.workload, "batch": args.batch, "precision": args.precision,
+               "tiles": args.tiles, "source_hash": source_hash(),
+               "calibration": {"copy_bytes": copy_bytes, "fetch_factor": ff, "write_factor": wf},
+               "fetch_bytes_per_launch": {}, "write_bytes_per_launch": {}, "bytes_per_launch": {},
+               "algorithmic_bytes_per_launch": alg,
+               "commands": [f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d <fetch> -o run -- {kern_cmd}",
+                            f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d <write> -o run -- {kern_cmd}"]}
+        for kind, d in sorted(per.items()):
+            if kind == "copy" or "fetch" not in d or "write" not in d:
+                continue
+            fb = ff * d["fetch"][1] / d["fetch"][0]
+            wb = wf * d["write"][1] / d["write"][0]
+            rec["fetch_bytes_per_launch"][kind] = fb
+            rec["write_bytes_per_launch"][kind] = wb
+            rec["bytes_per_launch"][kind] = fb + wb
+        path = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
+        json.dump(rec, open(path, "w"), indent=1)
+        lines = [f"# HBM traffic per launch: {args.workload}, {args.precision} branch states, "
+                 f"{args.batch}-branch waves", "", "Commands (repository root):", ""]
+        lines += [f"    {c}" for c in rec["commands"]]
+        lines += ["", f"FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled by what they read for "
+                  f"a plain {copy_bytes / 2**30:.0f} GiB copy kernel in the same run: fetch factor "
+                  f"{ff:.3f}, write factor {wf:.3f}.", "",
+                  "| kind | launches | fetch MB | write MB | total MB | algorithmic MB | total / algorithmic |",
+                  "|---|---|---|---|---|---|---|"]
+        for kind in rec["bytes_per_launch"]:
+            a = alg.get(kind)
+            t = rec["bytes_per_launch"][kind]
+            lines.append(f"| {kind} | {per[kind]['fetch'][0]} | {rec['fetch_bytes_per_launch'][kind] / 1e6:.2f} | "
+                         f"{rec['write_bytes_per_launch'][kind] / 1e6:.2f} | {t / 1e6:.2f} | "
+                         f"{'%.2f' % (a / 1e6) if a else '-'} | {'%.3f' % (t / a) if a else '-'} |")
+        lines += ["", f"Kernel sources hash: {rec['source_hash']} (bench.py uses these figures only while "
+                  f"the kernel sources hash to this value)."]
+        path = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.md")
+        open(path, "w").write("\n".join(lines) + "\n")
+        log(f"[summarise] wrote {path}")
+    return 0
+
+
+def auto_batch(pk, w, prec, total_bytes: int) -> int:
+    """Largest branch batch (at most n_t1) whose workspace fits in 85% of the
+    device memory."""
+    n_t1 = int(w.get("n_t1", 1))
+    base = pk.workspace_bytes(pk.params_from_workload(w, precision=pk.CHFPE_FP64, batch=1))
+    one = pk.workspace_bytes(pk.params_from_workload(w, precision=prec, batch=1))
+    two = pk.workspace_bytes(pk.params_from_workload(w, precision=prec, batch=2))
+    per = max(1, two - one)  # branch buffers of one more branch
+    fit = int((0.85 * total_bytes - base) // per)
+    return max(1, min(n_t1, fit))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,20 +282,45 @@ def main(argv=None):
     ap.add_argument("--timing-every", type=int, default=64,
                     help="bracket every k-th RK4 step's launches with HIP events")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--batch", type=int, default=1, help="t1 branches propagated together")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="t1 branches propagated together (0: as many as fit in 85%% of device "
+                         "memory, at most n_t1; two_mode_32: all 64 in one wave)")
     ap.add_argument("--precision", choices=["f64", "f32"], default="f64",
                     help="type of the propagated t1-branch states")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", choices=["bench", "kernels", "rk4"], default="bench",
-                    help="kernels: a few RK4 steps of the workload plus a plain copy of known "
-                         "size, for hardware-counter runs")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the planner's default tile shapes (no chfpe_autotune before warmup)")
+    ap.add_argument("--tiles", default="",
+                    help="NB,SPLIT,PC: fixed tile shapes (k_pblock blocks per task, lane-pair "
+                         "line solves 0/1, q-pass run positions per tile) instead of autotuning")
+    ap.add_argument("--mode", choices=["bench", "kernels", "rk4", "summarise", "precision"], default="bench",
+                    help="kernels: a few RK4 steps of the workload (single state, then one "
+                         "batched wave) plus a plain copy of known size, for hardware-counter "
+                         "runs; summarise: turn rocprofv3 output of the bench and kernels "
+                         "commands into the text summaries under profiles/ (no GPU)")
+    ap.add_argument("--ref-batch", type=int, default=0,
+                    help="precision: branch batch of the FP64 reference run (0: --batch)")
+    ap.add_argument("--trace-dir", help="summarise: rocprofv3 --kernel-trace --stats output folder")
+    ap.add_argument("--fetch-dir", help="summarise: rocprofv3 --pmc FETCH_SIZE output folder")
+    ap.add_argument("--write-dir", help="summarise: rocprofv3 --pmc WRITE_SIZE output folder")
+    ap.add_argument("--bench-json", help="summarise: the JSON line the traced bench run printed")
+    ap.add_argument("--kernels-json", help="summarise: the JSON line the counted kernels run printed")
     ap.add_argument("--rk4-steps", type=int, default=4, help="RK4 steps in --mode kernels")
     args = ap.parse_args(argv)
+    if args.mode == "summarise":
+        return summarise(args)
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the build targets a "
               f"single MI355X; sharding over t1 branches is described in DESIGN.md", file=sys.stderr)
         return 2
+
+    if args.tiles:
+        nb, split, pc = (int(x) for x in args.tiles.split(","))
+        os.environ["CHFPE_TUNE_PB_NB"] = str(nb)
+        os.environ["CHFPE_TUNE_PB_SPLIT"] = str(split)
+        os.environ["CHFPE_TUNE_Q_PC"] = str(pc)
+        args.no_autotune = True
 
     import numpy as np
     import torch
@@ -123,6 +336,10 @@ def main(argv=None):
     steps_per = rk4_steps(w) if w["kind"] == "2d" else int(w["eq_steps"]) + int(w["n_t"]) - 1
     torch.cuda.init()
     prec = pk.CHFPE_FP32 if args.precision == "f32" else pk.CHFPE_FP64
+    if args.mode == "rk4":
+        args.batch = 1  # propagation of one FP64 state: no branch buffers
+    elif args.batch <= 0:
+        args.batch = auto_batch(pk, w, prec, torch.cuda.get_device_properties(0).total_memory)
     solver = pk.Solver(pk.params_from_workload(w, precision=prec, batch=args.batch))
     S = solver.count
     log(f"[bench] workload={args.workload} values/state={S} rk4_steps/step={steps_per}")
@@ -148,12 +365,47 @@ def main(argv=None):
         solver.close()
         return 0
 
+    if args.mode == "precision":
+        # the whole hot path twice, FP64 then FP32 branch states: speedup and
+        # the FP32 error of R and of the 2D spectrum against the FP64 run
+        solver.close()
+        out = {"mode": "precision", "workload": args.workload}
+        res = {}
+        for prec_name, pcode, nb in (("f64", pk.CHFPE_FP64, args.ref_batch or args.batch),
+                                     ("f32", pk.CHFPE_FP32, args.batch)):
+            s = pk.Solver(pk.params_from_workload(w, precision=pcode, batch=nb))
+            tiles = s.tile_config() if args.no_autotune else s.autotune(1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.equilibrate(int(w["eq_steps"]), dt)
+            R = s.response_2d(w["A"], w["B"], w["C"], int(w["n_t1"]), int(w["n_t2"]),
+                              int(w["stride1"]), int(w["stride2"]), dt)
+            I = pk.spectrum_2d(R, int(w["stride1"]) * dt, int(w["stride2"]) * dt)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            s.close()
+            res[prec_name] = (R, I)
+            out[prec_name] = {"seconds": el, "updates_per_s": S * steps_per / el, "batch": nb, "tiles": tiles}
+            log(f"[precision] {prec_name}: {el:.2f} s")
+        (R64, I64), (R32, I32) = res["f64"], res["f32"]
+        out["speedup_f32_over_f64"] = out["f64"]["seconds"] / out["f32"]["seconds"]
+        out["R_rel_l2"] = float(np.linalg.norm(R32 - R64) / np.linalg.norm(R64))
+        out["spectrum_rel_l2"] = float(np.linalg.norm(I32 - I64) / np.linalg.norm(I64))
+        print(json.dumps(out), flush=True)
+        return 0
+
     if args.mode == "kernels":
         # the same kernels as a bench step, a few RK4 steps only; then a plain
         # copy of a known byte count as the counter calibration reference
+        solver.set_kernel_timing(1)  # every launch bracketed (and no graph capture)
         solver.equilibrate(0, 0.0)  # Boltzmann start on the device
         solver.propagate(args.rk4_steps, dt)
+        if w["kind"] == "2d":
+            # one wave of all batch branches, rk4_steps batched RK4 steps long
+            nb = max(1, args.batch)
+            solver.response_2d(w["A"], w["B"], w["C"], nb, args.rk4_steps + 1, 1, 1, dt)
         torch.cuda.synchronize()
+        kt = solver.kernel_times()
         nbytes = 1 << 30
         src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
@@ -161,7 +413,9 @@ def main(argv=None):
             pk.stream_copy(dst, src, nbytes)
         torch.cuda.synchronize()
         print(json.dumps({"mode": "kernels", "workload": args.workload, "rk4_steps": args.rk4_steps,
-                          "values_per_state": S, "copy_bytes": nbytes, "copies": 3}), flush=True)
+                          "values_per_state": S, "copy_bytes": nbytes, "copies": 3,
+                          "kernel_bytes": {k: v[2] for k, v in kt.items() if v[0] > 0},
+                          "kernel_ms": {k: v[1] for k, v in kt.items() if v[0] > 0}}), flush=True)
         solver.close()
         return 0
 
@@ -175,11 +429,22 @@ def main(argv=None):
         I = pk.spectrum_2d(R, int(w["stride1"]) * dt, int(w["stride2"]) * dt)
         return R, I
 
+    tiles = solver.tile_config()
+    if not args.no_autotune:
+        # tile shapes for this problem shape, kept by later contexts of the
+        # same shape (the rebuild at the start of every step)
+        t0 = time.perf_counter()
+        tiles = solver.autotune(2)
+        log(f"[bench] autotune {time.perf_counter() - t0:.2f} s: {tiles}")
     for i in range(args.warmup):
         log(f"[bench] warmup {i + 1}/{args.warmup}")
         one_step()
     torch.cuda.synchronize()
 
+    # a 16-byte copy marks the start of the timed region in kernel traces
+    # (the profile summaries keep only dispatches after the last copy)
+    mark = torch.zeros(32, dtype=torch.uint8, device="cuda")
+    pk.stream_copy(mark[16:], mark[:16], 16)
     times = []
     kcount, ktime, kbyte = {}, {}, {}
     for i in range(args.steps):
@@ -201,6 +466,8 @@ def main(argv=None):
     updates = float(S) * steps_per * args.steps
     value = updates / total
 
+    tiles_arg = "{},{},{}".format(tiles["request_pblock_blocks"], tiles["request_split"],
+                                  tiles["request_qpass_positions"])
     # roofline of the dominant kernel (largest share of the timed launches' time)
     share = {k: kt[k][0] * kt[k][1] for k in kt if kt[k][0] > 0}
     roofline = None
@@ -214,7 +481,8 @@ def main(argv=None):
             try:
                 rec = json.load(open(tf))
                 if (rec.get("source_hash") == source_hash() and dom in rec.get("bytes_per_launch", {})
-                        and rec.get("batch") == args.batch and rec.get("precision") == args.precision):
+                        and rec.get("batch") == args.batch and rec.get("precision") == args.precision
+                        and rec.get("tiles") in ("", tiles_arg)):
                     traffic = float(rec["bytes_per_launch"][dom])
             except (OSError, ValueError):
                 traffic = None
@@ -254,7 +522,8 @@ def main(argv=None):
         "config": {"workload": f"{args.workload}: 2 modes, 32^4 (q,p) grid, depth 3 (10 elements), "
                                f"equilibration 4000 + 2D THz-Raman 64 t1 x 256 t2 RK4 steps, dt {dt}",
                    "values_per_state": S, "rk4_steps_per_step": steps_per,
-                   "branch_batch": args.batch, "branch_precision": args.precision},
+                   "branch_batch": args.batch, "branch_precision": args.precision,
+                   "tiles": tiles, "tiles_arg": tiles_arg},
         "roofline": roofline,
         "path_roofline_16pass": step_alg,
         "cpu_baseline": cpu,

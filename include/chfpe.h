@@ -66,7 +66,7 @@ enum { CHFPE_FP64 = 0, CHFPE_FP32 = 1 };
  *     (batch x 5 extra state buffers of the branch type in the workspace),
  *     each wave's t2 loop as one captured HIP graph.
  * Limits: 1 <= M <= 3, 0 <= K <= 12, 5 <= N <= 48 on every axis, all
- * masses, beta, L > 0, one element below 2^31 points, and
+ * masses, beta, L > 0, one element below 2^29 points, and
  * exp(-beta H_sys/2) representable (> 1e-150) everywhere on the grid.
  */
 typedef struct {
@@ -206,6 +206,32 @@ int chfpe_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream
 int chfpe_set_kernel_timing(chfpe_ctx *ctx, int32_t every);
 int chfpe_kernel_times(chfpe_ctx *ctx, int32_t max_kinds, int64_t *counts, double *mean_ms,
                        double *mean_bytes, const char **names);
+
+/* Tile autotuner.  Times one RK4 step (after one untimed step), averaged
+ * over n_steps (1..1000), for each candidate tile shape: first the k_pblock
+ * shapes (blocks per task 1, 2, 4, 8 where the block fits, with and
+ * without lane-pair line solves), then the q-pass tile widths 4, 8, 16, 32
+ * (positions of the contiguous run per two-axis tile, as LDS allows) with
+ * the best k_pblock shape.  The path timed is the one the context spends
+ * most time in: the batched branch buffers (branch type) when batch > 1,
+ * else the FP64 single-state path.  The fastest shape is kept by this
+ * context and, for the rest of the process, by every later context of the
+ * same shape (M, K, grid, precision, batch); CHFPE_TUNE_* environment
+ * variables still override it.  Runs on scratch buffers only: the current
+ * state and W_eq are unchanged; a cached 2D-response graph is dropped.
+ * Synchronizes the stream.  EINVAL for n_steps out of range, EDEVICE if a
+ * trial fails (the previous shapes are then kept). */
+int chfpe_autotune(chfpe_ctx *ctx, int32_t n_steps);
+
+/* The tile shapes in use: out[0] k_pblock blocks per task, out[1] 1 if
+ * lines are solved by lane pairs, out[2] k_pblock threads per workgroup,
+ * out[3] run positions per tile of the stage-final q-pass, out[4] the same
+ * for the three-mode (q_2, q_3) pass (0 otherwise), out[5] threads of the
+ * stage-final q-pass; out[6..8] the requests these came from (blocks per
+ * task, lane pairs, run positions; 0, -1, 0 = planner default), which the
+ * CHFPE_TUNE_PB_NB, CHFPE_TUNE_PB_SPLIT and CHFPE_TUNE_Q_PC environment
+ * variables reproduce.  Writes min(n, 9) values and returns that count. */
+int chfpe_tile_config(const chfpe_ctx *ctx, int32_t *out, int32_t n);
 
 /* Message of the last error on this context (or of the last failed
  * chfpe_setup on this thread when ctx is NULL); never NULL. */

@@ -106,6 +106,10 @@ def lib():
     L.chfpe_set_kernel_timing.restype = ctypes.c_int
     L.chfpe_kernel_times.argtypes = [vp, i32, ctypes.POINTER(i64), dp, dp, ctypes.POINTER(ctypes.c_char_p)]
     L.chfpe_kernel_times.restype = ctypes.c_int
+    L.chfpe_autotune.argtypes = [vp, i32]
+    L.chfpe_autotune.restype = ctypes.c_int
+    L.chfpe_tile_config.argtypes = [vp, ctypes.POINTER(i32), i32]
+    L.chfpe_tile_config.restype = ctypes.c_int
     L.chfpe_last_error.argtypes = [vp]
     L.chfpe_last_error.restype = ctypes.c_char_p
     L.chfpe_destroy.argtypes = [vp]
@@ -313,6 +317,22 @@ class Solver:
 
     def set_kernel_timing(self, every: int):
         self._check(lib().chfpe_set_kernel_timing(self._ctx, int(every)))
+
+    def autotune(self, n_steps: int = 2) -> dict:
+        """chfpe_autotune; returns the tile shapes then in use."""
+        self._check(lib().chfpe_autotune(self._ctx, int(n_steps)))
+        return self.tile_config()
+
+    def tile_config(self) -> dict:
+        """chfpe_tile_config as a dict."""
+        out = (ctypes.c_int32 * 9)()
+        k = lib().chfpe_tile_config(self._ctx, out, 9)
+        if k < 0:
+            self._check(k)
+        keys = ("pblock_blocks_per_task", "pblock_split_lines", "pblock_threads", "qpass_positions",
+                "qpass_acc_positions", "qpass_threads", "request_pblock_blocks",
+                "request_split", "request_qpass_positions")
+        return {keys[i]: int(out[i]) for i in range(k)}
 
     def kernel_times(self) -> dict:
         """{kind: (timed launches, mean ms, mean algorithmic bytes)}."""

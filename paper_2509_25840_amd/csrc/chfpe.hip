@@ -18,6 +18,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -153,8 +155,8 @@ bool derive(const chfpe_params *p, Derived &d, std::string &err) {
   }
   d.E = (long long)d.Q * d.P;
   d.S = d.E * d.ne;
-  if (d.E >= (1LL << 31)) {
-    err = "one element must have fewer than 2^31 points";
+  if (d.E >= (1LL << 29)) {  // byte offsets within an element fit 32 bits
+    err = "one element must have fewer than 2^29 points";
     return false;
   }
   return true;
@@ -219,6 +221,23 @@ struct Launch {
 
 int pad8(int n) { return (n + 7) / 8 * 8; }
 
+// Tile shapes the autotuner picked, kept per problem shape for the rest of
+// the process (later contexts of the same shape start from them).
+struct TileChoice {
+  int pb_nb = 0, pb_split = -1, q_pc = 0;
+};
+std::mutex g_tune_mu;
+std::map<std::vector<long long>, TileChoice> g_tuned;
+
+std::vector<long long> tune_key(const Derived &d) {
+  std::vector<long long> k = {d.M, d.K, d.prec, d.B, d.batched ? 1 : 0};
+  for (int s = 0; s < 3; ++s) {
+    k.push_back(s < d.M ? d.Nq[s] : 0);
+    k.push_back(s < d.M ? d.Np[s] : 0);
+  }
+  return k;
+}
+
 int nmax_bucket(int n) {
   return n <= 8 ? 8 : n <= 12 ? 12 : n <= 16 ? 16 : n <= 24 ? 24 : n <= 32 ? 32 : 48;
 }
@@ -252,6 +271,7 @@ struct chfpe_ctx {
   std::string err = "no error";
   int tune_pb_nb = 0;   // blocks per k_pblock task (0: automatic)
   int tune_q_pc = 0;    // run positions per two-axis k_qpass tile (0: automatic)
+  int tune_pb_split = -1;  // k_pblock lines solved by lane pairs (-1: automatic)
   bool capturing = false;  // a HIP graph is being captured: no event timing
   bool use_graphs = true;
   // kernel timing
@@ -516,6 +536,7 @@ void plan(chfpe_ctx *c) {
     --nb;
   nb = std::min(nb, pb.nblocks);
   pb.nb = nb;
+  pb.split = c->tune_pb_split >= 0 ? (c->tune_pb_split != 0) : 1;
   // every thread row index rg + k RG (k < RPT) has an LDS slot
   const int tile_rows = std::max(nb * pb.rows, pb.RG * kPBlockRPT);
   pb.tileP = tile_rows * (NpM + 1);
@@ -933,6 +954,43 @@ int check_finite(chfpe_ctx *c, const double *W) {
   return CHFPE_OK;
 }
 
+// Milliseconds per RK4 step of the path the context spends most time in:
+// the batched branch buffers (branch type) when 2D responses are batched,
+// else the FP64 single-state buffers with u as the state.  One untimed step
+// first; returns < 0 on a launch or runtime error (message in c->err).
+template <typename T>
+double time_batched(chfpe_ctx *c, int n_steps, double dt) {
+  const Batch b = batch_of(c, c->d.B);
+  const RK4Bufs<T> r{(T *)c->bb[0], (T *)c->bb[1], (T *)c->bb[2], (T *)c->bb[3], (T *)c->bb[4]};
+  if (rk4<T>(c, b, r, 1, dt)) return -1.0;
+  hipEvent_t e0 = get_event(c), e1 = get_event(c);
+  if (!e0 || !e1) return -1.0;
+  (void)hipEventRecord(e0, c->stream);
+  const int rc = rk4<T>(c, b, r, n_steps, dt);
+  (void)hipEventRecord(e1, c->stream);
+  float ms = -1.f;
+  if (rc == CHFPE_OK && hipEventSynchronize(e1) == hipSuccess) (void)hipEventElapsedTime(&ms, e0, e1);
+  c->event_pool.push_back(e0);
+  c->event_pool.push_back(e1);
+  return rc ? -1.0 : (double)ms / n_steps;
+}
+
+double time_rk4_step(chfpe_ctx *c, int n_steps, double dt) {
+  if (c->d.batched)
+    return c->d.prec == CHFPE_FP32 ? time_batched<float>(c, n_steps, dt) : time_batched<double>(c, n_steps, dt);
+  if (rk4(c, c->u, 1, dt)) return -1.0;
+  hipEvent_t e0 = get_event(c), e1 = get_event(c);
+  if (!e0 || !e1) return -1.0;
+  (void)hipEventRecord(e0, c->stream);
+  const int rc = rk4(c, c->u, n_steps, dt);
+  (void)hipEventRecord(e1, c->stream);
+  float ms = -1.f;
+  if (rc == CHFPE_OK && hipEventSynchronize(e1) == hipSuccess) (void)hipEventElapsedTime(&ms, e0, e1);
+  c->event_pool.push_back(e0);
+  c->event_pool.push_back(e1);
+  return rc ? -1.0 : (double)ms / n_steps;
+}
+
 int ensure_rbuf(chfpe_ctx *c, size_t n) {
   if (n <= c->rbuf_cap) return CHFPE_OK;
   if (c->rbuf) {
@@ -1014,8 +1072,18 @@ int chfpe_setup(const chfpe_params *p, void *dev_workspace, size_t ws_bytes, voi
     for (int i = 0; i < 5; ++i) c->bb[i] = at(L.bbufs[i]);
 
   make_geom(c);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(tune_key(d));
+    if (it != g_tuned.end()) {
+      c->tune_pb_nb = it->second.pb_nb;
+      c->tune_pb_split = it->second.pb_split;
+      c->tune_q_pc = it->second.q_pc;
+    }
+  }
   if (const char *v = std::getenv("CHFPE_TUNE_PB_NB")) c->tune_pb_nb = std::atoi(v);
   if (const char *v = std::getenv("CHFPE_TUNE_Q_PC")) c->tune_q_pc = std::atoi(v);
+  if (const char *v = std::getenv("CHFPE_TUNE_PB_SPLIT")) c->tune_pb_split = std::atoi(v);
   if (const char *v = std::getenv("CHFPE_NO_GRAPH")) c->use_graphs = std::atoi(v) == 0;
   std::vector<double> F, Vp, pm, pg, sq, sp, wp, cc, tc, damp;
   std::vector<int> up, dn;
@@ -1332,6 +1400,74 @@ int chfpe_set_kernel_timing(chfpe_ctx *c, int32_t every) {
   c->timing_every = every;
   c->step_counter = 0;
   return CHFPE_OK;
+}
+
+int chfpe_autotune(chfpe_ctx *c, int32_t n_steps) {
+  if (!c) return CHFPE_EINVAL;
+  if (n_steps < 1 || n_steps > 1000) return fail(c, CHFPE_EINVAL, "need 1 <= n_steps <= 1000");
+  const Derived &d = c->d;
+  // the timed steps run on scratch buffers holding zeros (the work does not
+  // depend on the values); the cached wave graph holds the old tile shapes
+  HIPCHK(c, hipMemsetAsync(c->u, 0, sizeof(double) * (size_t)d.S, c->stream));
+  if (d.batched)
+    HIPCHK(c, hipMemsetAsync(c->bb[0], 0, (d.prec == CHFPE_FP32 ? 4 : 8) * (size_t)d.S * d.B, c->stream));
+  if (c->wave_graph) {
+    HIPCHK(c, hipGraphExecDestroy(c->wave_graph));
+    c->wave_graph = nullptr;
+  }
+  const int timing = c->timing_every;
+  c->timing_every = 0;
+  const double dt = 1e-3;
+  TileChoice best{c->tune_pb_nb, c->tune_pb_split, c->tune_q_pc};
+  double best_ms = 1e300;
+  auto restore = [&](int rc) {
+    c->tune_pb_nb = best.pb_nb;
+    c->tune_pb_split = best.pb_split;
+    c->tune_q_pc = best.q_pc;
+    plan(c);
+    c->timing_every = timing;
+    return rc;
+  };
+  auto trial = [&](const TileChoice &t, std::vector<std::vector<int>> &seen) -> int {
+    c->tune_pb_nb = t.pb_nb;
+    c->tune_pb_split = t.pb_split;
+    c->tune_q_pc = t.q_pc;
+    plan(c);
+    const std::vector<int> eff = {c->ln.pb.nb, c->ln.pb.split, c->ln.qf.pc, c->ln.qa.pc};
+    for (const auto &s : seen)
+      if (s == eff) return CHFPE_OK;  // same launches as a shape already timed
+    seen.push_back(eff);
+    const double ms = time_rk4_step(c, n_steps, dt);
+    if (ms < 0) return CHFPE_EDEVICE;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = t;
+    }
+    return CHFPE_OK;
+  };
+  // k_pblock shapes first (q tiles automatic), then q tiles with the best
+  std::vector<std::vector<int>> seen;
+  for (int split : {1, 0})
+    for (int nb : {1, 2, 4, 8})
+      if (trial(TileChoice{nb, split, best.q_pc}, seen)) return restore(fail(c, CHFPE_EDEVICE, "autotune step failed"));
+  const TileChoice pbest = best;
+  for (int pc : {4, 8, 16, 32})
+    if (trial(TileChoice{pbest.pb_nb, pbest.pb_split, pc}, seen)) return restore(fail(c, CHFPE_EDEVICE, "autotune step failed"));
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[tune_key(d)] = best;
+  }
+  return restore(last_launch_error(c));
+}
+
+int chfpe_tile_config(const chfpe_ctx *c, int32_t *out, int32_t n) {
+  if (!c || !out || n < 0) return CHFPE_EINVAL;
+  const int32_t v[9] = {c->ln.pb.nb,  c->ln.pb.split,    c->ln.pb_threads,
+                        c->ln.qf.pc,  c->ln.has_qa ? c->ln.qa.pc : 0, c->ln.qf_threads,
+                        c->tune_pb_nb, c->tune_pb_split, c->tune_q_pc};
+  const int k = n < 9 ? n : 9;
+  for (int i = 0; i < k; ++i) out[i] = v[i];
+  return k;
 }
 
 int chfpe_kernel_times(chfpe_ctx *c, int32_t max_kinds, int64_t *counts, double *mean_ms,

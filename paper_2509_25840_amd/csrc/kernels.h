@@ -154,6 +154,66 @@ __device__ __forceinline__ void compact_lds(T *G, const int base, const int stri
   }
 }
 
+// Same derivative for a line of exactly N values in LDS, solved by two
+// neighbouring lanes (lane bit 0 = half): each eliminates N/2 equations from
+// its own end of the line, the pair couples its last two unknowns through one
+// exchange, and each back-substitutes its half.  tridiag(1/3, 1, 1/3) is
+// persymmetric, so the far half is the same sweep on the mirrored line: the
+// mirror reverses the load order and flips the sign of the stencil (ca, cb),
+// and the coupling of the two last equations
+//   x_{H-1} + c x_H = d_own,  x_H + c x_{H-1} = d_partner  (c = cp_{H-1})
+// gives x_own = (d_own - c d_partner) / (1 - c^2) in either lane.
+// Both lanes of a pair must call this together.
+template <typename T, int N>
+__device__ __forceinline__ void compact_split(T *G, const int base, const int stride, const int half,
+                                              T ca, T cb) {
+  static_assert(N % 2 == 0 && N >= 4, "split solve needs an even line of at least 4");
+  constexpr int H = N / 2;
+  constexpr double cm = kThomas.cp[H - 1];
+  constexpr double inv1mc2 = 1.0 / (1.0 - cm * cm);
+  const int step = half ? -stride : stride;
+  const int start = base + (half ? (N - 1) * stride : 0);
+  if (half) {
+    ca = -ca;
+    cb = -cb;
+  }
+  T f[H + 2];
+#pragma unroll
+  for (int i = 0; i < H + 2; ++i) f[i] = G[start + i * step];
+  T d[H];
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    const T fm1 = i >= 1 ? f[i >= 1 ? i - 1 : 0] : T(0);
+    const T fm2 = i >= 2 ? f[i >= 2 ? i - 2 : 0] : T(0);
+    const T r = ca * (f[i + 1] - fm1) + cb * (f[i + 2] - fm2);
+    if (i == 0)
+      d[0] = r;
+    else  // d_i = (r_i - d_{i-1}/3) / pivot_i, one dependent FMA
+      d[i] = __builtin_fma(T(-kThomas.inv[i] / 3.0), d[i >= 1 ? i - 1 : 0], r * T(kThomas.inv[i]));
+  }
+  const T other = __shfl_xor(d[H - 1], 1);
+  T x = (d[H - 1] - T(cm) * other) * T(inv1mc2);
+  G[start + (H - 1) * step] = x;
+#pragma unroll
+  for (int i = H - 2; i >= 0; --i) {
+    x = d[i] - T(kThomas.cp[i]) * x;
+    G[start + i * step] = x;
+  }
+}
+
+// Element idx of a workgroup-uniform base pointer.  The byte offset is formed
+// in 32 bits, so the access takes the scalar-base form (one 32-bit offset
+// register shared by every array indexed alike); callers keep idx * sizeof(T)
+// below 2^32.
+template <typename T>
+__device__ __forceinline__ const T &at_u32(const T *__restrict__ base, const uint32_t idx) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + idx * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ T &at_u32(T *__restrict__ base, const uint32_t idx) {
+  return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + idx * (uint32_t)sizeof(T));
+}
+
 // ---------------------------------------------------------------------------
 // Geometry and tables passed by value to every kernel.
 // ---------------------------------------------------------------------------
@@ -214,6 +274,7 @@ struct PBlock {
   int bpq;           // blocks per q point (P / B)
   int RG;            // row groups; threads = cols * RG
   int tileP;         // padded values of one LDS field = nb * rows * (cols + 1)
+  int split;         // 1: two lanes per line (compact_split) where the line length allows
   int ntasks, nblk;
 };
 
@@ -258,7 +319,7 @@ struct QPass {
 // T: type of X and of the arithmetic; TO: type of out.  A batch of nbatch
 // states is laid out [branch][n][q][p]; tasks cover every (branch, n).
 template <typename T, typename TO, int NMAX, int RPT, int MM, bool PERTURB>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, (NMAX <= 24 || (NMAX == 32 && MM == 2)) ? 5 : NMAX <= 32 ? 4 : 3)
 k_pblock(const Geom g, const Tabs tb, const PBlock pb, const T *__restrict__ X, TO *__restrict__ out,
          const double *__restrict__ grad) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -306,43 +367,38 @@ k_pblock(const Geom g, const Tabs tb, const PBlock pb, const T *__restrict__ X, 
   const double dmp = PERTURB ? 0.0 : tb.damp[e];
   const double p_col = tb.pg[sa * kTab + col];
 
-  // ---- phase 1: rows R_k = rg + k RG of the run --------------------------------
-  // Row R = k RG + rg.  For two or three modes the host picks RG | rows, so
-  // the block of batch k, (k RG) / rows, is the same for the whole workgroup.
+  // ---- phase 1: rows R_k = k RG + rg of the run --------------------------------
+  // Two or three modes: the host picks RG | rows, so the RG rows of batch k lie
+  // in one block, (k RG) / rows, and all but the row index is uniform over the
+  // workgroup (table values of the q point come through scalar loads).  Rows
+  // past the run re-read block 0 and are not stored.  One mode: a block is one
+  // row and row R is block R.
   int off[RPT], qlk[RPT], rk[RPT], jok[RPT];
-  {
-    int blk = 0, r = rg;
-    while (r >= rows) {
-      r -= rows;
-      ++blk;
-    }
+  bool vk[RPT];
 #pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-      const int R = rg + k * pb.RG;
-      const bool valid = R < nrows;
-      int bl, rr;
-      if (NB == 2) {
-        bl = valid ? (k * pb.RG) / rows : 0;  // uniform; rows past the run re-read block 0
-        rr = valid ? (k * pb.RG) % rows + rg : rg;
-      } else {
-        bl = valid ? blk : 0;
-        rr = 0;
-      }
-      const int ob = b0 + bl;
+  for (int k = 0; k < RPT; ++k) {
+    if constexpr (NB == 2) {
+      const int R0 = k * pb.RG;
+      const int bl = R0 / rows;
+      vk[k] = bl < nbt;
+      const int ob = b0 + (vk[k] ? bl : 0);
       qlk[k] = ob / pb.bpq;
       jok[k] = ob - qlk[k] * pb.bpq;
-      rk[k] = rr;
-      off[k] = bl * pb.B + rr * cols + col;
-      r += pb.RG;
-      while (r >= rows) {
-        r -= rows;
-        ++blk;
-      }
+      rk[k] = (vk[k] ? R0 - bl * rows : 0) + rg;
+      off[k] = (vk[k] ? R0 * cols : 0) + rg * cols + col;
+    } else {
+      const int R = k * pb.RG + rg;
+      vk[k] = R < nrows;
+      const int ob = b0 + (vk[k] ? R : 0);
+      qlk[k] = ob / pb.bpq;
+      jok[k] = 0;
+      rk[k] = 0;
+      off[k] = (vk[k] ? R : 0) * cols + col;
     }
   }
   T hv[RPT];
 #pragma unroll
-  for (int k = 0; k < RPT; ++k) hv[k] = Xe[off[k]];
+  for (int k = 0; k < RPT; ++k) hv[k] = at_u32(Xe, off[k]);
   T pw[RPT];
   if (PERTURB) {
 #pragma unroll
@@ -367,8 +423,8 @@ k_pblock(const Geom g, const Tabs tb, const PBlock pb, const T *__restrict__ X, 
     for (int s = 0; s < MM; ++s)
 #pragma unroll
       for (int k = 0; k < RPT; ++k) {
-        hu[s][k] = Xu[s][off[k]];
-        hd[s][k] = Xd[s][off[k]];
+        hu[s][k] = at_u32(Xu[s], off[k]);
+        hd[s][k] = at_u32(Xd[s], off[k]);
       }
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
@@ -396,12 +452,29 @@ k_pblock(const Geom g, const Tabs tb, const PBlock pb, const T *__restrict__ X, 
       pw[k] = acc;
     }
   }
+  // keep the pointwise terms computed here: sunk past the barriers, their
+  // inputs would stay live (in registers) through the line solves
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) asm volatile("" : "+v"(pw[k]));
   __syncthreads();
 
   // ---- phase 2: rows of Ga and columns of Gb ------------------------------------
-  {
-    const int nla = nrows;
-    const int nlb = NB == 2 ? nbt * cols : 0;
+  const int nla = nrows;
+  const int nlb = NB == 2 ? nbt * cols : 0;
+  if (pb.split && cols == NMAX && (NB == 1 || rows == NMAX)) {
+    // two lanes per line; the pair (2l, 2l+1) is in one wave
+    const T ca_a = T(g.dp_ca[sa]), cb_a = T(g.dp_cb[sa]);
+    const T ca_b = T(g.dp_ca[NB == 2 ? sb : sa]), cb_b = T(g.dp_cb[NB == 2 ? sb : sa]);
+    for (int hl = tid; hl < 2 * (nla + nlb); hl += blockDim.x) {
+      const int l = hl >> 1;
+      const bool is_row = l < nla;
+      const int lb = l - nla;
+      const int blk = lb / NMAX;
+      const int base = is_row ? l * cp : blk * NMAX * cp + (lb - blk * NMAX);
+      compact_split<T, NMAX>(is_row ? Ga : Gb, base, is_row ? 1 : cp, hl & 1, is_row ? ca_a : ca_b,
+                             is_row ? cb_a : cb_b);
+    }
+  } else {
     for (int l = tid; l < nla + nlb; l += blockDim.x) {
       T *G;
       int base, stride, N;
@@ -424,16 +497,7 @@ k_pblock(const Geom g, const Tabs tb, const PBlock pb, const T *__restrict__ X, 
         ca = T(g.dp_ca[NB == 2 ? sb : sa]);
         cb = T(g.dp_cb[NB == 2 ? sb : sa]);
       }
-      if (N == NMAX) {
-        T f[NMAX];
-#pragma unroll
-        for (int i = 0; i < NMAX; ++i) f[i] = G[base + i * stride];
-        compact_deriv_exact<T, NMAX>(f, ca, cb);
-#pragma unroll
-        for (int i = 0; i < NMAX; ++i) G[base + i * stride] = f[i];
-      } else {
-        compact_lds<T>(G, base, stride, N, ca, cb);
-      }
+      compact_lds<T>(G, base, stride, N, ca, cb);
     }
   }
   __syncthreads();
@@ -441,11 +505,10 @@ k_pblock(const Geom g, const Tabs tb, const PBlock pb, const T *__restrict__ X, 
   // ---- phase 3 ----------------------------------------------------------------
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
-    const int R = rg + k * pb.RG;
-    const int li = R * cp + col;
+    const int li = (rg + k * pb.RG) * cp + col;
     T v = pw[k] + Ga[li];
     if (NB == 2) v += Gb[li];
-    if (owner && R < nrows) Oe[off[k]] = TO(v);
+    if (owner && vk[k]) at_u32(Oe, off[k]) = TO(v);
   }
 }
 
@@ -481,8 +544,8 @@ __device__ __forceinline__ T field_at(const Geom &g, const Tabs &tb, const T *__
   const int dn = tb.dn[e * 3 + s];
   const double vp = tb.Vp[s * kTab + (ql / g.QS[s]) % g.Nq[s]];
   T Gv = T(tb.F[(long long)s * g.Q + ql]) * w;
-  if (up >= 0) Gv += T(vp) * Xb[(long long)up * g.E + rel];
-  if (dn >= 0) Gv += T(vp * tb.cc[e * 3 + s]) * Xb[(long long)dn * g.E + rel];
+  if (up >= 0) Gv += T(vp) * at_u32(Xb + (long long)up * g.E, rel);
+  if (dn >= 0) Gv += T(vp * tb.cc[e * 3 + s]) * at_u32(Xb + (long long)dn * g.E, rel);
   return Gv;
 }
 
@@ -522,10 +585,12 @@ k_qpass(const Geom g, const Tabs tb, const QPass qp, const T *__restrict__ X, TO
   const long long ebase = (long long)ea * g.E;
   const T *Xb = X + (long long)br * g.ne * g.E;
 
+  // element i of this thread's a-line: uniform pointer (element base plus
+  // i strides) with the thread's 32-bit offset lrel
   T f[NMAX];
 #pragma unroll
   for (int i = 0; i < NMAX; ++i)
-    f[i] = (active && i < Na) ? X[ebase + lrel + i * qp.sa] : T(0);
+    f[i] = (active && i < Na) ? at_u32(X + ebase + (long long)i * qp.sa, lrel) : T(0);
 
   // LDS tile [ja][jb][c] with row stride (Nb + 1) * pc: the pad keeps the
   // b-line reads of different ja in different banks
@@ -584,26 +649,30 @@ k_qpass(const Geom g, const Tabs tb, const QPass qp, const T *__restrict__ X, TO
     if (i < Na) {
       T kv = ka * d[i];
       if (TWO) kv += kb * lds[i * rs + jb * qp.pc + c];
-      const long long idx = ebase + lrel + i * qp.sa;
+      const long long ui = ebase + (long long)i * qp.sa;  // uniform part of the index
+      TO &tacc = at_u32(Tacc + ui, lrel);
       if (EPI == EPI_ACC) {
-        Tacc[idx] = TO(T(Tacc[idx]) + kv);
+        tacc = TO(T(tacc) + kv);
       } else {
-        kv += T(Tacc[idx]);
+        kv += T(tacc);
+        TO &xov = at_u32(xo + ui, lrel);
         if (EPI == EPI_OUT) {
-          xo[idx] = TO(kv);
+          xov = TO(kv);
         } else if (EPI == EPI_S1) {
-          yacc[idx] = TO(f[i] + h6 * kv);
-          xo[idx] = TO(f[i] + h2 * kv);
+          at_u32(yacc + ui, lrel) = TO(f[i] + h6 * kv);
+          xov = TO(f[i] + h2 * kv);
         } else if (EPI == EPI_S2) {
-          const T yv = T(y[idx]);
-          yacc[idx] = TO(T(yacc[idx]) + h3 * kv);
-          xo[idx] = TO(yv + h2 * kv);
+          const T yv = T(at_u32(y + ui, lrel));
+          TO &ya = at_u32(yacc + ui, lrel);
+          ya = TO(T(ya) + h3 * kv);
+          xov = TO(yv + h2 * kv);
         } else if (EPI == EPI_S3) {
-          const T yv = T(y[idx]);
-          yacc[idx] = TO(T(yacc[idx]) + h3 * kv);
-          xo[idx] = TO(yv + h1 * kv);
+          const T yv = T(at_u32(y + ui, lrel));
+          TO &ya = at_u32(yacc + ui, lrel);
+          ya = TO(T(ya) + h3 * kv);
+          xov = TO(yv + h1 * kv);
         } else {  // EPI_S4
-          xo[idx] = TO(T(yacc[idx]) + h6 * kv);
+          xov = TO(T(at_u32(yacc + ui, lrel)) + h6 * kv);
         }
       }
     }

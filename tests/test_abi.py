@@ -93,4 +93,7 @@ def test_null_context_calls_are_rejected(binding):
     assert L.chfpe_equilibrate(None, 1, 0.1) == binding.CHFPE_EINVAL
     assert L.chfpe_propagate(None, 1, 0.1) == binding.CHFPE_EINVAL
     assert L.chfpe_state_count(None) == 0
+    assert L.chfpe_autotune(None, 1) == binding.CHFPE_EINVAL
+    buf = (ctypes.c_int32 * 6)()
+    assert L.chfpe_tile_config(None, buf, 6) == binding.CHFPE_EINVAL
     L.chfpe_destroy(None)

@@ -58,6 +58,8 @@ SMALL = {
     "m2_n12_k3": wl.workload("two_mode_32", Nq=[12, 12], Np=[12, 12], K=3),
     "m3_n8_k2": wl.workload("three_mode_24", Nq=[8, 7, 8], Np=[8, 9, 7], K=2),
     "m3_n6_k3": wl.workload("three_mode_24", Nq=[6, 6, 6], Np=[6, 6, 6], K=3),
+    # square 8 x 8 (p_2, p_3) blocks: lane-pair line solves, ragged q and p_1
+    "m3_p8_k2": wl.workload("three_mode_24", Nq=[7, 6, 8], Np=[9, 8, 8], K=2),
 }
 
 
@@ -263,7 +265,7 @@ def test_response_2d_fp32_branches(pk, name):
     assert err < 1e-4
 
 
-@pytest.mark.parametrize("kind", ["RTT", "TRT", "TTR"])
+@pytest.mark.parametrize("kind", ["RTT", "TRT", "TTR", "TTT"])
 def test_response_2d_orderings_and_resolved_stride(pk, kind):
     """The three THz-Raman orderings (operator swaps through the same entry
     point) with a physically resolved stride of 8 RK4 steps per sample."""
@@ -276,3 +278,49 @@ def test_response_2d_orderings_and_resolved_stride(pk, kind):
         s.equilibrate(10, 0.004)
         got = s.response_2d(A, B, C, 4, 5, 8, 8, 0.004)
     assert rel_l2(got, ref) < FP64_TOL
+
+
+@pytest.mark.parametrize("split", ["0", "1"])
+def test_pblock_line_solvers_agree(pk, monkeypatch, split):
+    """Lane-pair and single-lane line solves of k_pblock both match the oracle
+    (two-mode 12^4 and one-mode 48-point lines)."""
+    monkeypatch.setenv("CHFPE_TUNE_PB_SPLIT", split)
+    for name, w in (("m2_n12_k3", SMALL["m2_n12_k3"]), ("m1_n48", wl.workload("one_mode_48"))):
+        say(f"[pblock split={split}] {name}")
+        W = phys_state(w, seed=6)
+        ref = orc.rk4(w, W, 2, 0.002)
+        with solver(pk, w) as s:
+            s.set_state(W)
+            s.propagate(2, 0.002)
+            got = s.get_state().reshape(W.shape)
+        assert rel_l2(got, ref) < 1e-13
+
+
+def test_autotune_keeps_state_and_results(pk):
+    """chfpe_autotune times tile shapes on scratch buffers: the state is
+    unchanged, the chosen shapes are reported, later steps and batched
+    responses still match the oracle, and a new context of the same shape
+    starts from the tuned shapes."""
+    w = SMALL["m2_n12_k3"]
+    A, B = _ops(2)
+    say("[autotune]")
+    Weq = orc.equilibrate(w, 10, 0.004)
+    ref = orc.response_2d(w, A, B, A, Weq, 5, 4, 1, 2, 0.004)
+    W = phys_state(w, seed=7)
+    ref_steps = orc.rk4(w, W, 2, 0.002)
+    p = pk.params_from_workload(w, precision=pk.CHFPE_FP64, batch=5)
+    with pk.Solver(p) as s:
+        s.equilibrate(10, 0.004)
+        s.set_state(W)
+        before = s.get_state()
+        cfg = s.autotune(1)
+        say(f"    tuned {cfg}")
+        assert cfg["pblock_blocks_per_task"] >= 1 and cfg["qpass_positions"] >= 1
+        assert cfg["pblock_split_lines"] in (0, 1)
+        assert np.array_equal(s.get_state(), before)
+        s.propagate(2, 0.002)
+        assert rel_l2(s.get_state().reshape(W.shape), ref_steps) < 1e-13
+        got = s.response_2d(A, B, A, 5, 4, 1, 2, 0.004)
+    assert rel_l2(got, ref) < FP64_TOL
+    with pk.Solver(p) as s2:
+        assert s2.tile_config() == cfg

@@ -183,9 +183,10 @@ def draw_perturbed(w: dict, seed: int, rel: float = 0.2) -> dict:
 
 
 def response_types(w: dict) -> dict:
-    """Operator triples (A, B, C) of the three 2D THz-Raman orderings of
-    Sec. V: Raman-THz-THz (A = Pi), THz-Raman-THz (B = Pi), THz-THz-Raman
-    (C = Pi); the other operators are the dipole mu."""
+    """Operator triples (A, B, C) of the second-order responses of Sec. II C:
+    the three 2D THz-Raman orderings Raman-THz-THz (A = Pi), THz-Raman-THz
+    (B = Pi) and THz-THz-Raman (C = Pi), and the all-dipole second-order
+    (THz/IR) response TTT; operators other than Pi are the dipole mu."""
     M = int(w["M"])
     mu, pi = _dipole(M), _polarizability(M)
-    return {"RTT": (pi, mu, mu), "TRT": (mu, pi, mu), "TTR": (mu, mu, pi)}
+    return {"RTT": (pi, mu, mu), "TRT": (mu, pi, mu), "TTR": (mu, mu, pi), "TTT": (mu, mu, mu)}
