@@ -209,6 +209,7 @@ struct Launch {
   PBlock pb{};
   size_t pb_lds = 0;
   int pb_threads = 256, pb_nmax = 48;
+  int pb_rpt = 4;  // rows per k_pblock thread (3 where it tiles the 24-row blocks exactly)
   // strided-axis passes of one stage: qa (three modes only, accumulates into
   // t) then qf (applies the stage update); qx: the p_1 excitation pass of
   // three modes.
@@ -495,7 +496,7 @@ void plan_two(chfpe_ctx *c, int a, int b, int run, std::vector<int> rest, QPass 
   const Derived &d = c->d;
   const int Na = axis_len(d, a), Nb = axis_len(d, b);
   int pc = c->tune_q_pc > 0 ? c->tune_q_pc : 16;
-  const size_t lds_cap = c->tune_q_pc > 0 ? 160 * 1024 : 80 * 1024;
+  const size_t lds_cap = 160 * 1024;  // a whole CU's LDS: one wide tile beats two narrow ones
   while (pc > 1 && ((size_t)Na * (Nb + 1) * pc * sizeof(double) > lds_cap || std::max(Na, Nb) * pc > kQThreadsMax))
     pc /= 2;
   out = make_qpass(c, a, b, run, rest, pc);
@@ -537,14 +538,15 @@ void plan(chfpe_ctx *c) {
   nb = std::min(nb, pb.nblocks);
   pb.nb = nb;
   pb.split = c->tune_pb_split >= 0 ? (c->tune_pb_split != 0) : 1;
+  ln.pb_nmax = nmax_bucket(std::max(pb.rows, pb.cols));
+  ln.pb_rpt = (ln.pb_nmax == 24 && pb.NB == 2 && nb * pb.rows == 3 * pb.RG) ? 3 : kPBlockRPT;
   // every thread row index rg + k RG (k < RPT) has an LDS slot
-  const int tile_rows = std::max(nb * pb.rows, pb.RG * kPBlockRPT);
+  const int tile_rows = std::max(nb * pb.rows, pb.RG * ln.pb_rpt);
   pb.tileP = tile_rows * (NpM + 1);
   pb.ntasks = d.ne * ((pb.nblocks + nb - 1) / nb);
   pb.nblk = pad8(pb.ntasks);
   ln.pb_lds = (size_t)pb.NB * pb.tileP * sizeof(double);
   ln.pb_threads = pb.RG * pb.cols;
-  ln.pb_nmax = nmax_bucket(std::max(pb.rows, pb.cols));
   // strided-axis passes
   if (M == 1) {
     ln.has_qa = false;
@@ -661,13 +663,24 @@ Batch batch_of(const chfpe_ctx *c, int nb) {
   return b;
 }
 
-template <typename T, typename TO, int NMAX, int MM, bool PERTURB>
-void launch_pblock_nm(chfpe_ctx *c, const Batch &b, const T *X, TO *out, const double *grad) {
+template <typename T, typename TO, int NMAX, int RPT, int MM, bool PERTURB>
+void launch_pblock_rpt(chfpe_ctx *c, const Batch &b, const T *X, TO *out, const double *grad) {
   const Launch &ln = c->ln;
-  auto kern = k_pblock<T, TO, NMAX, kPBlockRPT, MM, PERTURB>;
+  auto kern = k_pblock<T, TO, NMAX, RPT, MM, PERTURB>;
   allow_lds(kern, ln.pb_lds);
   hipLaunchKernelGGL(kern, dim3(b.pb.nblk), dim3(ln.pb_threads), ln.pb_lds, c->stream, b.g, c->tb, b.pb, X,
                      out, grad);
+}
+
+template <typename T, typename TO, int NMAX, int MM, bool PERTURB>
+void launch_pblock_nm(chfpe_ctx *c, const Batch &b, const T *X, TO *out, const double *grad) {
+  if constexpr (NMAX == 24 && MM >= 2) {
+    if (c->ln.pb_rpt == 3) {
+      launch_pblock_rpt<T, TO, NMAX, 3, MM, PERTURB>(c, b, X, out, grad);
+      return;
+    }
+  }
+  launch_pblock_rpt<T, TO, NMAX, kPBlockRPT, MM, PERTURB>(c, b, X, out, grad);
 }
 
 template <typename T, typename TO, int NMAX, bool PERTURB>

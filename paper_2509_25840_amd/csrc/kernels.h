@@ -559,10 +559,23 @@ k_qpass(const Geom g, const Tabs tb, const QPass qp, const T *__restrict__ X, TO
   T *lds = reinterpret_cast<T *>(smem_raw);
   const int task = xcd_task(blockIdx.x, qp.nblk);
   if (task >= qp.ntasks) return;
-  const int chunk = task % qp.nchunk;
-  const int t2 = task / qp.nchunk;
-  const int rest = t2 % qp.nrest;
-  const int ea = t2 / qp.nrest;  // (branch, element)
+  // Task order.  A pass with a p-axis field (which reads hierarchy
+  // neighbours) varies the element fastest: the tiles of all elements at one
+  // position run close together on one XCD, so the neighbour reads hit its
+  // L2.  Other passes walk each element's memory in order (DRAM locality).
+  const int ne_all = g.ne * g.nbatch;
+  int ea, chunk, rest;  // ea: (branch, element)
+  if constexpr (FA == FP || FB == FP) {
+    ea = task % ne_all;
+    const int t2 = task / ne_all;
+    chunk = t2 % qp.nchunk;
+    rest = t2 / qp.nchunk;
+  } else {
+    chunk = task % qp.nchunk;
+    const int t2 = task / qp.nchunk;
+    rest = t2 % qp.nrest;
+    ea = t2 / qp.nrest;
+  }
   const int br = ea / g.ne;
   const int e = ea - br * g.ne;
   const int p0 = chunk * qp.pc;

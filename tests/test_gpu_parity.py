@@ -60,6 +60,8 @@ SMALL = {
     "m3_n6_k3": wl.workload("three_mode_24", Nq=[6, 6, 6], Np=[6, 6, 6], K=3),
     # square 8 x 8 (p_2, p_3) blocks: lane-pair line solves, ragged q and p_1
     "m3_p8_k2": wl.workload("three_mode_24", Nq=[7, 6, 8], Np=[9, 8, 8], K=2),
+    # 24 x 24 (p_2, p_3) blocks as in the 24^6 workload: three rows per thread
+    "m3_p24_k2": wl.workload("three_mode_24", Nq=[5, 6, 5], Np=[5, 24, 24], K=2),
 }
 
 
