@@ -293,11 +293,20 @@ def main(argv=None):
     ap.add_argument("--tiles", default="",
                     help="NB,SPLIT,PC: fixed tile shapes (k_pblock blocks per task, lane-pair "
                          "line solves 0/1, q-pass run positions per tile) instead of autotuning")
-    ap.add_argument("--mode", choices=["bench", "kernels", "rk4", "summarise", "precision"], default="bench",
+    ap.add_argument("--mode", choices=["bench", "kernels", "rk4", "summarise", "precision", "closure"],
+                    default="bench",
                     help="kernels: a few RK4 steps of the workload (single state, then one "
                          "batched wave) plus a plain copy of known size, for hardware-counter "
                          "runs; summarise: turn rocprofv3 output of the bench and kernels "
                          "commands into the text summaries under profiles/ (no GPU)")
+    ap.add_argument("--closure-draws", type=int, default=16, help="closure: training draws (seeds 0..)")
+    ap.add_argument("--closure-held", type=int, default=4, help="closure: held-out draws (seeds 1000..)")
+    ap.add_argument("--closure-steps", type=int, default=3000, help="closure: Adam steps")
+    ap.add_argument("--closure-lr", type=float, default=3e-3)
+    ap.add_argument("--closure-snap", default="1000,400,50",
+                    help="closure: fine-run equilibration steps, steps after each excitation, snapshot spacing")
+    ap.add_argument("--judge", default="",
+                    help="closure: EQ,N_T1,N_T2,STRIDE of the judged responses (default: the workload's)")
     ap.add_argument("--ref-batch", type=int, default=0,
                     help="precision: branch batch of the FP64 reference run (0: --batch)")
     ap.add_argument("--trace-dir", help="summarise: rocprofv3 --kernel-trace --stats output folder")
@@ -363,6 +372,70 @@ def main(argv=None):
                           "kernels": {k: {"ms": v[1], "GBps": v[2] / (v[1] * 1e-3) / 1e9}
                                       for k, v in kt.items() if v[0] > 0}}), flush=True)
         solver.close()
+        return 0
+
+    if args.mode == "closure":
+        # train the closure of the 2:1 coarse grid of this workload on fine
+        # runs of seeded draws, then judge it on held-out draws and on the
+        # workload itself against the fine-grid FP64 spectrum
+        import copy
+        import paper_2509_25840_amd.closure as clo
+        solver.close()
+        wc = copy.deepcopy(w)
+        wc["Nq"] = [n // 2 for n in w["Nq"]]
+        wc["Np"] = [n // 2 for n in w["Np"]]
+        n_eq, n_prop, every = (int(x) for x in args.closure_snap.split(","))
+        t0 = time.perf_counter()
+        draws = []
+        for sd in range(args.closure_draws):
+            wd = wl.draw_perturbed(wc, sd)
+            draws.append((wd, clo.fine_moments(wd, n_eq, n_prop, every, dt)))
+            log(f"[closure] moments of draw {sd}")
+        data = clo.training_set(draws)
+        t_data = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        tr, hist = clo.train(data, args.closure_steps, args.closure_lr)
+        t_train = time.perf_counter() - t0
+        log(f"[closure] trained: loss {hist[0]:.4e} -> {hist[-1]:.4e} ({t_train:.2f} s)")
+        if args.judge:
+            j_eq, j1, j2, js = (int(x) for x in args.judge.split(","))
+        else:
+            j_eq, j1, j2, js = int(w["eq_steps"]), int(w["n_t1"]), int(w["n_t2"]), int(w["stride1"])
+
+        def spectrum(wk, nb, sv=None):
+            with pk.Solver(pk.params_from_workload(wk, precision=pk.CHFPE_FP64, batch=nb)) as s:
+                if sv is not None:
+                    s.set_closure(sv)
+                torch.cuda.synchronize()
+                ts = time.perf_counter()
+                s.equilibrate(j_eq, dt)
+                R = s.response_2d(wk["A"], wk["B"], wk["C"], j1, j2, js, js, dt)
+                I = pk.spectrum_2d(R, js * dt, js * dt)
+                torch.cuda.synchronize()
+                return R, I, time.perf_counter() - ts
+
+        judged = [("nominal", wc)] + [(f"held_{1000 + k}", wl.draw_perturbed(wc, 1000 + k))
+                                      for k in range(args.closure_held)]
+        rows = []
+        for name, wj in judged:
+            wf = clo.fine_of(wj)
+            nbf = auto_batch(pk, {**wf, "n_t1": j1}, pk.CHFPE_FP64, torch.cuda.get_device_properties(0).total_memory)
+            nbc = auto_batch(pk, {**wj, "n_t1": j1}, pk.CHFPE_FP64, torch.cuda.get_device_properties(0).total_memory)
+            Rf, If, tf = spectrum(wf, nbf)
+            Rp, Ip, tp = spectrum(wj, nbc)
+            Rc, Ic, tc = spectrum(wj, nbc, clo.entries(tr.prm, wj))
+            e = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+            rows.append({"case": name, "fine_s": tf, "coarse_s": tp, "closure_s": tc,
+                         "spectrum_err_plain": e(Ip, If), "spectrum_err_closure": e(Ic, If),
+                         "R_err_plain": e(Rp, Rf), "R_err_closure": e(Rc, Rf)})
+            log(f"[closure] {name}: plain {rows[-1]['spectrum_err_plain']:.3e} "
+                f"closure {rows[-1]['spectrum_err_closure']:.3e} fine {tf:.2f} s coarse {tc:.2f} s")
+        out = {"mode": "closure", "fine_workload": args.workload, "coarse_grid": wc["Nq"] + wc["Np"],
+               "draws": args.closure_draws, "snapshots": args.closure_snap, "steps": args.closure_steps,
+               "lr": args.closure_lr, "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
+               "data_s": t_data, "train_s": t_train, "judge": [j_eq, j1, j2, js], "cases": rows,
+               "speedup_closure_vs_fine": float(np.mean([r["fine_s"] / r["closure_s"] for r in rows]))}
+        print(json.dumps(out), flush=True)
         return 0
 
     if args.mode == "precision":

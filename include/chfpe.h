@@ -233,6 +233,68 @@ int chfpe_autotune(chfpe_ctx *ctx, int32_t n_steps);
  * variables reproduce.  Writes min(n, 9) values and returns that count. */
 int chfpe_tile_config(const chfpe_ctx *ctx, int32_t *out, int32_t n);
 
+/* ---- Learned per-axis closure (coarse grids) -------------------------------
+ * The paper discretises every axis with the compact scheme of Sec. III B on
+ * one grid.  A closure lets a coarse grid (half the points per axis of a fine
+ * grid on the same box) stand in for the fine one: along each grid axis a,
+ * the compact system A y = B f / h becomes A y = (B + S_a) f / h, with S_a
+ * skew-symmetric on the first two off-diagonals (S[i][i+k] = -S[i+k][i] = s,
+ * k = 1, 2), which keeps A D skew like the plain scheme.  The entries s are
+ * the output of a network of one hidden layer (16 features -> 32 tanh units
+ * -> 1; BF16 weights and activations in MFMA products, FP32 accumulation),
+ * trained on this device against fine-grid states of the solver itself.
+ * Rows of the network: one per (axis, entry), axes in id order (q_1..q_M,
+ * p_1..p_M), entries S[i][i+1] for i < N_a - 1, then S[i][i+2] for
+ * i < N_a - 2.  Parameters (FP32, 577): W1[16][32], b1[32], W2[32], b2. */
+
+/* Number of rows, sum over axes of 2 N_a - 3; EINVAL for invalid params. */
+int32_t chfpe_closure_rows(const chfpe_params *coarse);
+
+/* Features of every row (host, rows x 16 FP32): u, u^2, |u| (u: the entry's
+ * midpoint over the half box), [k == 2], [p axis], h / sigma (sigma: thermal
+ * width, 1/(omega sqrt(beta m)) for q, sqrt(m/beta) for p), omega/1.6,
+ * g3 sigma_q/(m omega^2), g4 sigma_q^2/(m omega^2), V_SL sigma_q / V_LL,
+ * zeta, gamma, beta/2, m, [entry touches the box edge], 1.  axis_of_row
+ * (may be NULL) receives each row's axis id. */
+int chfpe_closure_features(const chfpe_params *coarse, float *feat, int32_t *axis_of_row);
+
+/* Training statistics of the context's current state, which must be on a
+ * fine grid (every axis even, 10..32 points): with x = R h (2:1 cell
+ * averages), T = R(D_a h) and r = T - D_a^coarse x for every coarse line,
+ * the loss sum ||r - A^{-1} S_a x / h||^2 of axis a is
+ * s^T G_a s - 2 b_a^T s + c_a, compared with t_a = sum ||T||^2.  ADDS G_a
+ * (P_a x P_a row-major, P_a = 2 N_a - 3, axes concatenated), b_a
+ * (concatenated) and (c_a, t_a) (2 per axis) into the host arrays, so
+ * calls over several states accumulate.  Uses the context's scratch
+ * buffers (not the state or W_eq); synchronizes its stream. */
+int chfpe_closure_moments(chfpe_ctx *fine, double *G, double *b, double *ct);
+
+/* s for every row at parameters prm (host arrays). */
+int chfpe_closure_eval(const float *prm, const float *feat, int32_t rows, float *s, void *hip_stream);
+
+/* grad = d(sum_rows gs[row] s[row]) / d(prm) (host arrays; one forward and
+ * backward pass, as in training). */
+int chfpe_closure_grad(const float *prm, const float *feat, int32_t rows, const float *gs, float *grad,
+                       void *hip_stream);
+
+/* n_steps Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, step lr) of the mean
+ * over groups of (s^T G s - 2 b^T s + c) / t, all on the device in one
+ * workgroup.  Group q owns rows [group_start[q], group_start[q+1]) (covering
+ * 0..rows) with G (P_q x P_q, groups concatenated), b, and (c, t) in ct.
+ * prm, adam_m, adam_v (577 each) are read and written back; adam_t0 is the
+ * number of steps already taken; loss (n_steps, may be NULL) receives the
+ * loss at the parameters each step starts from. */
+int chfpe_closure_train(const float *feat, int32_t rows, int32_t n_groups, const int32_t *group_start,
+                        const double *G, const double *b, const double *ct, float *prm, float *adam_m,
+                        float *adam_v, int32_t adam_t0, int32_t n_steps, float lr, float *loss,
+                        void *hip_stream);
+
+/* Use the closure entries s (one per row, FP64) in every right-hand side and
+ * excitation of this context from now on; NULL restores the plain scheme.
+ * EINVAL unless the context holds FP64 states and every axis has at most
+ * 16 points. */
+int chfpe_set_closure(chfpe_ctx *ctx, const double *s);
+
 /* Message of the last error on this context (or of the last failed
  * chfpe_setup on this thread when ctx is NULL); never NULL. */
 const char *chfpe_last_error(const chfpe_ctx *ctx);

@@ -71,12 +71,15 @@ def force(w: dict, q, s: int, eps: float = 1e-30):
     return np.imag(potential(w, qc)) / eps
 
 
-def generator(w: dict, symmetrised: bool = True):
+def generator(w: dict, symmetrised: bool = True, deriv=None):
     """(G, f): the sparse generator G acting on h (stacked elements) and the
     factor f = exp(-beta H/2) on the grid, so that dW/dt = f * (G @ (W / f)).
 
     With symmetrised=False the couplings of Eq. (eq:HEOM) are discretized on
     W itself (G then acts on W and f = 1); kept to show that form is unstable.
+    deriv(axis, N, h), if given, supplies the first-derivative matrix of each
+    grid axis (axis ids 0..M-1: q_s, M..2M-1: p_s) in place of the plain
+    compact one (used for coarse grids with a closure).
     """
     M, K = w["M"], w["K"]
     Nq, Np = list(w["Nq"]), list(w["Np"])
@@ -97,8 +100,9 @@ def generator(w: dict, symmetrised: bool = True):
             out = sp.kron(out, mat, format="csr")
         return out
 
-    Dq = [kron_axis(derivative_matrix(Nq[s], hq[s]), s) for s in range(M)]
-    Dp = [kron_axis(derivative_matrix(Np[s], hp[s]), M + s) for s in range(M)]
+    dm = deriv if deriv is not None else (lambda axis, N, h: derivative_matrix(N, h))
+    Dq = [kron_axis(dm(s, Nq[s], hq[s]), s) for s in range(M)]
+    Dp = [kron_axis(dm(M + s, Np[s], hp[s]), M + s) for s in range(M)]
     F = [force(w, q, s) for s in range(M)]
     Vp = [w["VLL"][s] + w["VSL"][s] * q[s] for s in range(M)]
 

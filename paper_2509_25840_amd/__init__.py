@@ -16,7 +16,8 @@ import numpy as np
 
 __all__ = ["Params", "Optical", "Solver", "ChfpeError", "lib", "params_from_workload",
            "optical_from_dict", "workspace_bytes", "stream_copy", "spectrum_1d", "spectrum_2d",
-           "LIB_PATH"]
+           "closure_rows", "closure_features", "closure_eval", "closure_grad", "ClosureTrainer",
+           "CLOSURE_PARAMS", "LIB_PATH"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libchfpe.so")
@@ -110,6 +111,22 @@ def lib():
     L.chfpe_autotune.restype = ctypes.c_int
     L.chfpe_tile_config.argtypes = [vp, ctypes.POINTER(i32), i32]
     L.chfpe_tile_config.restype = ctypes.c_int
+    fp = ctypes.POINTER(ctypes.c_float)
+    ip = ctypes.POINTER(i32)
+    L.chfpe_closure_rows.argtypes = [P]
+    L.chfpe_closure_rows.restype = i32
+    L.chfpe_closure_features.argtypes = [P, fp, ip]
+    L.chfpe_closure_features.restype = ctypes.c_int
+    L.chfpe_closure_moments.argtypes = [vp, dp, dp, dp]
+    L.chfpe_closure_moments.restype = ctypes.c_int
+    L.chfpe_closure_eval.argtypes = [fp, fp, i32, fp, vp]
+    L.chfpe_closure_eval.restype = ctypes.c_int
+    L.chfpe_closure_grad.argtypes = [fp, fp, i32, fp, fp, vp]
+    L.chfpe_closure_grad.restype = ctypes.c_int
+    L.chfpe_closure_train.argtypes = [fp, i32, i32, ip, dp, dp, dp, fp, fp, fp, i32, i32, ctypes.c_float, fp, vp]
+    L.chfpe_closure_train.restype = ctypes.c_int
+    L.chfpe_set_closure.argtypes = [vp, dp]
+    L.chfpe_set_closure.restype = ctypes.c_int
     L.chfpe_last_error.argtypes = [vp]
     L.chfpe_last_error.restype = ctypes.c_char_p
     L.chfpe_destroy.argtypes = [vp]
@@ -165,6 +182,88 @@ def stream_copy(dst, src, nbytes: int, stream=None) -> None:
                                  ctypes.c_size_t(nbytes), ctypes.c_void_p(s.cuda_stream))
     if rc != 0:
         raise ChfpeError(rc, "stream copy failed")
+
+
+def _fptr(a: np.ndarray):
+    assert a.dtype == np.float32 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def _iptr(a: np.ndarray):
+    assert a.dtype == np.int32 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _lib_check(rc: int):
+    if rc != 0:
+        raise ChfpeError(rc, lib().chfpe_last_error(None).decode())
+
+
+CLOSURE_PARAMS = 16 * 32 + 32 + 32 + 1
+
+
+def closure_rows(p: Params) -> int:
+    n = int(lib().chfpe_closure_rows(ctypes.byref(p)))
+    if n < 0:
+        raise ChfpeError(n, lib().chfpe_last_error(None).decode())
+    return n
+
+
+def closure_features(p: Params):
+    """(features rows x 16 float32, axis id of every row)."""
+    n = closure_rows(p)
+    feat = np.zeros((n, 16), dtype=np.float32)
+    axis = np.zeros(n, dtype=np.int32)
+    _lib_check(lib().chfpe_closure_features(ctypes.byref(p), _fptr(feat), _iptr(axis)))
+    return feat, axis
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def closure_eval(prm, feat, stream=None) -> np.ndarray:
+    prm = np.ascontiguousarray(prm, dtype=np.float32)
+    feat = np.ascontiguousarray(feat, dtype=np.float32)
+    s = np.zeros(feat.shape[0], dtype=np.float32)
+    _lib_check(lib().chfpe_closure_eval(_fptr(prm), _fptr(feat), feat.shape[0], _fptr(s), _stream_ptr(stream)))
+    return s
+
+
+def closure_grad(prm, feat, gs, stream=None) -> np.ndarray:
+    prm = np.ascontiguousarray(prm, dtype=np.float32)
+    feat = np.ascontiguousarray(feat, dtype=np.float32)
+    gs = np.ascontiguousarray(gs, dtype=np.float32)
+    g = np.zeros(CLOSURE_PARAMS, dtype=np.float32)
+    _lib_check(lib().chfpe_closure_grad(_fptr(prm), _fptr(feat), feat.shape[0], _fptr(gs), _fptr(g),
+                                        _stream_ptr(stream)))
+    return g
+
+
+class ClosureTrainer:
+    """Adam state and parameters of the closure network (FP32 host copies);
+    every step runs in chfpe_closure_train."""
+
+    def __init__(self, prm):
+        self.prm = np.ascontiguousarray(prm, dtype=np.float32).copy()
+        self.m = np.zeros(CLOSURE_PARAMS, dtype=np.float32)
+        self.v = np.zeros(CLOSURE_PARAMS, dtype=np.float32)
+        self.t = 0
+
+    def train(self, feat, group_start, G, b, ct, n_steps: int, lr: float, stream=None) -> np.ndarray:
+        feat = np.ascontiguousarray(feat, dtype=np.float32)
+        gst = np.ascontiguousarray(group_start, dtype=np.int32)
+        G = np.ascontiguousarray(G, dtype=np.float64)
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        ct = np.ascontiguousarray(ct, dtype=np.float64)
+        loss = np.zeros(max(1, n_steps), dtype=np.float32)
+        _lib_check(lib().chfpe_closure_train(_fptr(feat), feat.shape[0], len(gst) - 1, _iptr(gst), _dptr(G),
+                                             _dptr(b), _dptr(ct), _fptr(self.prm), _fptr(self.m), _fptr(self.v),
+                                             self.t, int(n_steps), float(lr), _fptr(loss), _stream_ptr(stream)))
+        self.t += int(n_steps)
+        return loss[:n_steps]
 
 
 def _dptr(a: np.ndarray):
@@ -314,6 +413,32 @@ class Solver:
         v = ctypes.c_double()
         self._check(lib().chfpe_observe(self._ctx, ctypes.byref(o), ctypes.byref(v)))
         return v.value
+
+    def closure_moments(self):
+        """chfpe_closure_moments of the current (fine-grid) state:
+        (list of G_a, list of b_a, array of (c_a, t_a)) for the 2:1 coarse grid."""
+        M = int(self.params.M)
+        N = [int(self.params.Nq[s]) // 2 for s in range(M)] + [int(self.params.Np[s]) // 2 for s in range(M)]
+        P = [2 * n - 3 for n in N]
+        G = np.zeros(sum(p * p for p in P))
+        b = np.zeros(sum(P))
+        ct = np.zeros(2 * 2 * M)
+        self._check(lib().chfpe_closure_moments(self._ctx, _dptr(G), _dptr(b), _dptr(ct)))
+        Gs, bs, go, bo = [], [], 0, 0
+        for p in P:
+            Gs.append(G[go:go + p * p].reshape(p, p))
+            bs.append(b[bo:bo + p])
+            go += p * p
+            bo += p
+        return Gs, bs, ct.reshape(2 * M, 2)
+
+    def set_closure(self, s):
+        """chfpe_set_closure (None restores the plain scheme)."""
+        if s is None:
+            self._check(lib().chfpe_set_closure(self._ctx, None))
+            return
+        a = np.ascontiguousarray(s, dtype=np.float64)
+        self._check(lib().chfpe_set_closure(self._ctx, _dptr(a)))
 
     def set_kernel_timing(self, every: int):
         self._check(lib().chfpe_set_kernel_timing(self._ctx, int(every)))

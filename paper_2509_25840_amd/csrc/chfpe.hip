@@ -23,7 +23,10 @@
 #include <string>
 #include <vector>
 
+#include <type_traits>
+
 #include "chfpe.h"
+#include "closure.h"
 #include "kernels.h"
 
 using namespace chfpe;
@@ -164,7 +167,7 @@ bool derive(const chfpe_params *p, Derived &d, std::string &err) {
 
 // Workspace layout (byte offsets, 256-aligned).
 struct Layout {
-  size_t F, VpQ, Vp, pm, pg, gA, gB, Cw, wp, sq, sp, up, dn, cc, tc, damp, partial, scal, flag;
+  size_t F, VpQ, Vp, pm, pg, gA, gB, Cw, wp, sq, sp, up, dn, cc, tc, damp, partial, scal, flag, clos;
   size_t bufs[7];
   size_t bbufs[5];  // batched branch buffers: y, yacc, xa, xb, t (B states each)
   size_t total;
@@ -198,6 +201,7 @@ Layout layout(const Derived &d) {
   L.partial = take(sizeof(double) * kPartials);
   L.scal = take(sizeof(double) * 16);
   L.flag = take(sizeof(int) * 16);
+  L.clos = take(sizeof(double) * 6 * 8 * kTab);  // closure stencil weights, [axis][orientation][4][kTab]
   for (int i = 0; i < 7; ++i) L.bufs[i] = take(sizeof(double) * (size_t)d.S);
   const size_t tsz = d.prec == CHFPE_FP32 ? sizeof(float) : sizeof(double);
   for (int i = 0; i < 5; ++i) L.bbufs[i] = d.batched ? take(tsz * (size_t)d.S * d.B) : 0;
@@ -274,6 +278,7 @@ struct chfpe_ctx {
   int tune_q_pc = 0;    // run positions per two-axis k_qpass tile (0: automatic)
   int tune_pb_split = -1;  // k_pblock lines solved by lane pairs (-1: automatic)
   bool capturing = false;  // a HIP graph is being captured: no event timing
+  bool closure_on = false; // right-hand sides use the closure stencil weights (tb.clos)
   bool use_graphs = true;
   // kernel timing
   int timing_every = 0;
@@ -663,9 +668,23 @@ Batch batch_of(const chfpe_ctx *c, int nb) {
   return b;
 }
 
+// Closure variants of the kernels exist for FP64 states with every axis in a
+// bucket of at most 16 points (chfpe_set_closure enforces this).
+template <typename T, typename TO, int NMAX>
+constexpr bool kClosureBuilt = std::is_same<T, double>::value && std::is_same<TO, double>::value && NMAX <= 16;
+
 template <typename T, typename TO, int NMAX, int RPT, int MM, bool PERTURB>
 void launch_pblock_rpt(chfpe_ctx *c, const Batch &b, const T *X, TO *out, const double *grad) {
   const Launch &ln = c->ln;
+  if constexpr (kClosureBuilt<T, TO, NMAX>) {
+    if (c->closure_on) {
+      auto kern = k_pblock<T, TO, NMAX, RPT, MM, PERTURB, true>;
+      allow_lds(kern, ln.pb_lds);
+      hipLaunchKernelGGL(kern, dim3(b.pb.nblk), dim3(ln.pb_threads), ln.pb_lds, c->stream, b.g, c->tb, b.pb,
+                         X, out, grad);
+      return;
+    }
+  }
   auto kern = k_pblock<T, TO, NMAX, RPT, MM, PERTURB>;
   allow_lds(kern, ln.pb_lds);
   hipLaunchKernelGGL(kern, dim3(b.pb.nblk), dim3(ln.pb_threads), ln.pb_lds, c->stream, b.g, c->tb, b.pb, X,
@@ -707,6 +726,15 @@ void launch_pblock_t(chfpe_ctx *c, const Batch &b, const T *X, TO *out, const do
 template <typename T, typename TO, int NMAX, bool TWO, int EPI, int FA, int FB>
 void launch_q_n(chfpe_ctx *c, const Batch &b, const QPass &qp, int threads, size_t lds, const T *X, TO *Tacc,
                 const TO *y, TO *yacc, TO *xo, const double *grad, double dt) {
+  if constexpr (kClosureBuilt<T, TO, NMAX>) {
+    if (c->closure_on) {
+      auto kern = k_qpass<T, TO, NMAX, TWO, EPI, FA, FB, true>;
+      allow_lds(kern, lds);
+      hipLaunchKernelGGL(kern, dim3(qp.nblk), dim3(threads), lds, c->stream, b.g, c->tb, qp, X, Tacc, y, yacc,
+                         xo, grad, dt);
+      return;
+    }
+  }
   auto kern = k_qpass<T, TO, NMAX, TWO, EPI, FA, FB>;
   allow_lds(kern, lds);
   hipLaunchKernelGGL(kern, dim3(qp.nblk), dim3(threads), lds, c->stream, b.g, c->tb, qp, X, Tacc, y, yacc,
@@ -1019,6 +1047,111 @@ int ensure_rbuf(chfpe_ctx *c, size_t n) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// closure helpers (host)
+// ---------------------------------------------------------------------------
+// Axis ids 0..M-1 are q_s, M..2M-1 are p_s; lengths and spacings per id.
+void axis_table(const chfpe_params *p, int M, int *N, double *h, double *L) {
+  for (int a = 0; a < 2 * M; ++a) {
+    const int s = a % M;
+    N[a] = a < M ? p->Nq[s] : p->Np[s];
+    L[a] = a < M ? p->Lq[s] : p->Lp[s];
+    h[a] = 2.0 * L[a] / N[a];
+  }
+}
+
+// Lines along axis a of a state [element][axis 0..2M-1] with lengths N.
+AxisLines axis_lines(const int *N, int nd, int a, long long ne) {
+  AxisLines al{};
+  long long stride = 1, E = 1;
+  for (int d = nd - 1; d >= 0; --d) {
+    if (d == a) al.inner = stride;
+    stride *= N[d];
+  }
+  E = stride;
+  al.N = N[a];
+  al.E = E;
+  al.outer = E / (al.inner * N[a]);
+  al.nlines = ne * al.inner * al.outer;
+  return al;
+}
+
+// A^{-1} and A^{-T} A^{-1} of the N x N matrix tridiag(1/3, 1, 1/3) (FP64,
+// Gauss-Jordan on the small dense matrix).
+void compact_inverse(int N, std::vector<double> &Ai, std::vector<double> &K) {
+  std::vector<double> A(N * N, 0.0);
+  Ai.assign(N * N, 0.0);
+  for (int i = 0; i < N; ++i) {
+    A[i * N + i] = 1.0;
+    if (i > 0) A[i * N + i - 1] = 1.0 / 3.0;
+    if (i + 1 < N) A[i * N + i + 1] = 1.0 / 3.0;
+    Ai[i * N + i] = 1.0;
+  }
+  for (int col = 0; col < N; ++col) {  // diagonally dominant: no pivoting needed
+    const double piv = A[col * N + col];
+    for (int j = 0; j < N; ++j) {
+      A[col * N + j] /= piv;
+      Ai[col * N + j] /= piv;
+    }
+    for (int r = 0; r < N; ++r) {
+      if (r == col) continue;
+      const double f = A[r * N + col];
+      if (f == 0.0) continue;
+      for (int j = 0; j < N; ++j) {
+        A[r * N + j] -= f * A[col * N + j];
+        Ai[r * N + j] -= f * Ai[col * N + j];
+      }
+    }
+  }
+  K.assign(N * N, 0.0);
+  for (int a = 0; a < N; ++a)
+    for (int b = 0; b < N; ++b) {
+      double v = 0.0;
+      for (int n = 0; n < N; ++n) v += Ai[n * N + a] * Ai[n * N + b];
+      K[a * N + b] = v;
+    }
+}
+
+int nmax_of(int n) { return nmax_bucket(n); }
+
+void launch_axis_deriv(hipStream_t st, const double *X, double *Y, const double *Yadd, double alpha,
+                       const AxisLines &al, double h) {
+  const double ca = 7.0 / 9.0 / h, cb = 1.0 / 36.0 / h;
+  const dim3 grid((unsigned)((al.nlines + 255) / 256));
+  switch (nmax_of(al.N)) {
+    case 8: hipLaunchKernelGGL(k_axis_deriv<8>, grid, dim3(256), 0, st, X, Y, Yadd, alpha, al, ca, cb); break;
+    case 12: hipLaunchKernelGGL(k_axis_deriv<12>, grid, dim3(256), 0, st, X, Y, Yadd, alpha, al, ca, cb); break;
+    case 16: hipLaunchKernelGGL(k_axis_deriv<16>, grid, dim3(256), 0, st, X, Y, Yadd, alpha, al, ca, cb); break;
+    case 24: hipLaunchKernelGGL(k_axis_deriv<24>, grid, dim3(256), 0, st, X, Y, Yadd, alpha, al, ca, cb); break;
+    default: hipLaunchKernelGGL(k_axis_deriv<32>, grid, dim3(256), 0, st, X, Y, Yadd, alpha, al, ca, cb); break;
+  }
+}
+
+// Device scratch owned by one closure call (freed on every exit path).
+struct DevScratch {
+  std::vector<void *> ptrs;
+  ~DevScratch() {
+    for (void *q : ptrs) (void)hipFree(q);
+  }
+  template <typename X>
+  X *get(size_t n) {
+    void *q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(X)) != hipSuccess) return nullptr;
+    ptrs.push_back(q);
+    return static_cast<X *>(q);
+  }
+};
+
+// Rows of the closure network for a coarse problem: one per (axis, skew
+// entry), axes in id order, entries S[i][i+1] (i < N-1) then S[i][i+2].
+int closure_rows(const chfpe_params *p) {
+  int n = 0;
+  for (int a = 0; a < 2 * p->M; ++a) n += 2 * (a < p->M ? p->Nq[a % p->M] : p->Np[a % p->M]) - 3;
+  return n;
+}
+
+int fail_g(int code, const std::string &msg) { return fail(nullptr, code, msg); }
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -1153,6 +1286,7 @@ int chfpe_setup(const chfpe_params *p, void *dev_workspace, size_t ws_bytes, voi
   c->tb.cc = c->cc;
   c->tb.tc = c->tc;
   c->tb.damp = c->damp;
+  c->tb.clos = reinterpret_cast<const double *>(at(L.clos));
   *out = c;
   return CHFPE_OK;
 }
@@ -1512,6 +1646,279 @@ void chfpe_destroy(chfpe_ctx *c) {
   if (c->rbuf) (void)hipFree(c->rbuf);
   if (c->own_ws && c->ws) (void)hipFree(c->ws);
   delete c;
+}
+
+// ---------------------------------------------------------------------------
+// learned per-axis closure
+// ---------------------------------------------------------------------------
+int32_t chfpe_closure_rows(const chfpe_params *p) {
+  Derived d;
+  std::string err;
+  if (!p || !derive(p, d, err)) return CHFPE_EINVAL;
+  return closure_rows(p);
+}
+
+int chfpe_closure_features(const chfpe_params *p, float *feat, int32_t *axis_of_row) {
+  Derived d;
+  std::string err;
+  if (!p || !feat || !derive(p, d, err)) return fail_g(CHFPE_EINVAL, err.empty() ? "invalid arguments" : err);
+  const int M = p->M;
+  int N[6];
+  double h[6], L[6];
+  axis_table(p, M, N, h, L);
+  int row = 0;
+  for (int a = 0; a < 2 * M; ++a) {
+    const int s = a % M;
+    const double m = p->m[s], om = p->omega[s], beta = p->beta;
+    const double sig_q = 1.0 / (om * std::sqrt(beta * m));
+    const double sig = a < M ? sig_q : std::sqrt(m / beta);
+    for (int e = 0; e < 2 * N[a] - 3; ++e) {
+      const int k = e < N[a] - 1 ? 1 : 2;
+      const int i = e < N[a] - 1 ? e : e - (N[a] - 1);
+      const double xi = -L[a] + (i + 0.5) * h[a], xk = -L[a] + (i + k + 0.5) * h[a];
+      const double u = 0.5 * (xi + xk) / L[a];
+      const int edge = std::min(i, N[a] - 1 - (i + k));
+      const double f[kClosFeat] = {u, u * u, std::fabs(u), k == 2 ? 1.0 : 0.0, a >= M ? 1.0 : 0.0, h[a] / sig,
+                                   om / 1.6, p->g3[s] * sig_q / (m * om * om),
+                                   p->g4[s] * sig_q * sig_q / (m * om * om), p->V_SL[s] * sig_q / p->V_LL[s],
+                                   p->zeta[s], p->gamma[s], beta / 2.0, m, edge == 0 ? 1.0 : 0.0, 1.0};
+      for (int q = 0; q < kClosFeat; ++q) feat[row * kClosFeat + q] = (float)f[q];
+      if (axis_of_row) axis_of_row[row] = a;
+      ++row;
+    }
+  }
+  return CHFPE_OK;
+}
+
+int chfpe_closure_moments(chfpe_ctx *c, double *G, double *b, double *ct) {
+  if (!c || !G || !b || !ct) return CHFPE_EINVAL;
+  const Derived &d = c->d;
+  const int M = d.M, nd = 2 * M;
+  int Nf[6], Nc[6];
+  double hf[6], Lf[6];
+  axis_table(&c->prm, M, Nf, hf, Lf);
+  for (int a = 0; a < nd; ++a) {
+    if (Nf[a] % 2 || Nf[a] / 2 < 5 || Nf[a] / 2 > 16)
+      return fail(c, CHFPE_EINVAL, "closure moments need even fine axes with 10..32 points");
+    Nc[a] = Nf[a] / 2;
+  }
+  const long long ne = d.ne;
+  long long Ec = 1;
+  for (int a = 0; a < nd; ++a) Ec *= Nc[a];
+  // coarse x, T, r in xa (3 coarse states fit in one fine state buffer)
+  double *xc = c->xa, *Tc = c->xa + ne * Ec, *rc = c->xa + 2 * ne * Ec;
+  Restrict rs{};
+  rs.nd = nd;
+  {
+    long long sc = 1, sf = 1;
+    for (int a = nd - 1; a >= 0; --a) {
+      rs.dc[a] = Nc[a];
+      rs.sc[a] = sc;
+      rs.sf[a] = sf;
+      sc *= Nc[a];
+      sf *= Nf[a];
+    }
+    rs.Ec = sc;
+    rs.Ef = sf;
+    rs.total = ne * sc;
+  }
+  const dim3 rgrid((unsigned)((rs.total + 255) / 256));
+  hipLaunchKernelGGL(k_restrict, rgrid, dim3(256), 0, c->stream, c->y, xc, rs);
+  DevScratch ds;
+  size_t goff = 0, boff = 0;
+  for (int a = 0; a < nd; ++a) {
+    const int N = Nc[a], P = 2 * N - 3;
+    const double hc = 2.0 * hf[a];
+    // target T = R(D_fine y) and residual r = T - D_coarse x
+    launch_axis_deriv(c->stream, c->y, c->t, nullptr, 1.0, axis_lines(Nf, nd, a, ne), hf[a]);
+    hipLaunchKernelGGL(k_restrict, rgrid, dim3(256), 0, c->stream, c->t, Tc, rs);
+    const AxisLines al = axis_lines(Nc, nd, a, ne);
+    launch_axis_deriv(c->stream, xc, rc, Tc, -1.0, al, hc);
+    const long long lpb = std::max<long long>(kMomLines, (al.nlines + 1023) / 1024);
+    const int nblk = (int)((al.nlines + lpb - 1) / lpb);
+    const int nmom = 2 * N * N + 2;
+    double *part = ds.get<double>((size_t)nblk * nmom);
+    double *mom = ds.get<double>(nmom);
+    double *dAi = ds.get<double>(N * N), *dK = ds.get<double>(N * N);
+    double *dG = ds.get<double>(P * P), *db = ds.get<double>(P);
+    if (!part || !mom || !dAi || !dK || !dG || !db) return fail(c, CHFPE_ENOMEM, "closure moments scratch");
+    std::vector<double> Ai, K;
+    compact_inverse(N, Ai, K);
+    HIPCHK(c, hipMemcpyAsync(dAi, Ai.data(), N * N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(dK, K.data(), N * N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(k_line_moments, dim3(nblk), dim3(256), 0, c->stream, xc, rc, Tc, al, lpb, part);
+    hipLaunchKernelGGL(k_sum_blocks, dim3((nmom + 255) / 256), dim3(256), 0, c->stream, part, nblk, nmom, mom);
+    hipLaunchKernelGGL(k_gram, dim3((P * P + P + 255) / 256), dim3(256), 0, c->stream, mom, dAi, dK, N, hc, dG,
+                       db);
+    std::vector<double> hG(P * P), hb(P), hm(nmom);
+    HIPCHK(c, hipMemcpyAsync(hG.data(), dG, P * P * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(hb.data(), db, P * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(hm.data(), mom, nmom * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int v = 0; v < P * P; ++v) G[goff + v] += hG[v];
+    for (int v = 0; v < P; ++v) b[boff + v] += hb[v];
+    ct[2 * a] += hm[2 * N * N];
+    ct[2 * a + 1] += hm[2 * N * N + 1];
+    goff += (size_t)P * P;
+    boff += P;
+  }
+  return last_launch_error(c);
+}
+
+// Converts host FP32 features to device BF16.
+static short *upload_features(DevScratch &ds, const float *feat, int rows, hipStream_t st) {
+  float *df = ds.get<float>((size_t)rows * kClosFeat);
+  short *dh = ds.get<short>((size_t)rows * kClosFeat);
+  if (!df || !dh) return nullptr;
+  if (hipMemcpyAsync(df, feat, (size_t)rows * kClosFeat * sizeof(float), hipMemcpyHostToDevice, st) != hipSuccess)
+    return nullptr;
+  hipLaunchKernelGGL(k_to_bf16, dim3((rows * kClosFeat + 255) / 256), dim3(256), 0, st, df, dh, rows * kClosFeat);
+  return dh;
+}
+
+int chfpe_closure_eval(const float *prm, const float *feat, int32_t rows, float *s, void *hip_stream) {
+  if (!prm || !feat || !s || rows < 1 || rows > (1 << 20)) return fail_g(CHFPE_EINVAL, "invalid arguments");
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  DevScratch ds;
+  short *dfeat = upload_features(ds, feat, rows, st);
+  float *dp = ds.get<float>(kClosParams), *ds_ = ds.get<float>(rows);
+  if (!dfeat || !dp || !ds_) return fail_g(CHFPE_ENOMEM, "closure eval scratch");
+  if (hipMemcpyAsync(dp, prm, kClosParams * sizeof(float), hipMemcpyHostToDevice, st) != hipSuccess)
+    return fail_g(CHFPE_EDEVICE, "copy");
+  const int ntiles = (rows + 15) / 16;
+  hipLaunchKernelGGL(k_clos_eval, dim3(std::min(1024, (ntiles + 3) / 4)), dim3(256), 0, st, dp, dfeat, rows, ds_);
+  if (hipGetLastError() != hipSuccess) return fail_g(CHFPE_EDEVICE, "closure eval launch");
+  if (hipMemcpyAsync(s, ds_, rows * sizeof(float), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail_g(CHFPE_EDEVICE, "closure eval copy");
+  return CHFPE_OK;
+}
+
+int chfpe_closure_grad(const float *prm, const float *feat, int32_t rows, const float *gs, float *grad,
+                       void *hip_stream) {
+  if (!prm || !feat || !gs || !grad || rows < 1 || rows > (1 << 20))
+    return fail_g(CHFPE_EINVAL, "invalid arguments");
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  DevScratch ds;
+  short *dfeat = upload_features(ds, feat, rows, st);
+  float *dp = ds.get<float>(kClosParams), *dgs = ds.get<float>(rows), *dg = ds.get<float>(kClosParams);
+  if (!dfeat || !dp || !dgs || !dg) return fail_g(CHFPE_ENOMEM, "closure grad scratch");
+  if (hipMemcpyAsync(dp, prm, kClosParams * sizeof(float), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(dgs, gs, rows * sizeof(float), hipMemcpyHostToDevice, st) != hipSuccess)
+    return fail_g(CHFPE_EDEVICE, "copy");
+  hipLaunchKernelGGL(k_clos_grad, dim3(1), dim3(256), 0, st, dp, dfeat, rows, dgs, dg);
+  if (hipGetLastError() != hipSuccess) return fail_g(CHFPE_EDEVICE, "closure grad launch");
+  if (hipMemcpyAsync(grad, dg, kClosParams * sizeof(float), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail_g(CHFPE_EDEVICE, "closure grad copy");
+  return CHFPE_OK;
+}
+
+int chfpe_closure_train(const float *feat, int32_t rows, int32_t n_groups, const int32_t *group_start,
+                        const double *G, const double *b, const double *ct, float *prm, float *adam_m,
+                        float *adam_v, int32_t adam_t0, int32_t n_steps, float lr, float *loss, void *hip_stream) {
+  if (!feat || !group_start || !G || !b || !ct || !prm || !adam_m || !adam_v || rows < 1 || rows > (1 << 20) ||
+      n_groups < 1 || n_steps < 0 || n_steps > 1000000 || adam_t0 < 0 || !(lr > 0.f))
+    return fail_g(CHFPE_EINVAL, "invalid arguments");
+  if (group_start[0] != 0 || group_start[n_groups] != rows) return fail_g(CHFPE_EINVAL, "groups must cover the rows");
+  std::vector<int> gof(rows);
+  std::vector<long long> goff(n_groups);
+  std::vector<int> boff(n_groups);
+  long long gtot = 0;
+  int btot = 0;
+  for (int q = 0; q < n_groups; ++q) {
+    const int P = group_start[q + 1] - group_start[q];
+    if (P < 1) return fail_g(CHFPE_EINVAL, "empty group");
+    goff[q] = gtot;
+    boff[q] = btot;
+    gtot += (long long)P * P;
+    btot += P;
+    for (int r = group_start[q]; r < group_start[q + 1]; ++r) gof[r] = q;
+    if (!(ct[2 * q + 1] > 0.0)) return fail_g(CHFPE_EINVAL, "group target norm must be positive");
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  DevScratch ds;
+  short *dfeat = upload_features(ds, feat, rows, st);
+  int *dgs = ds.get<int>(n_groups + 1), *dgof = ds.get<int>(rows), *dboff = ds.get<int>(n_groups);
+  long long *dgoff = ds.get<long long>(n_groups);
+  double *dG = ds.get<double>(gtot), *db = ds.get<double>(btot), *dct = ds.get<double>(2 * n_groups);
+  float *dp = ds.get<float>(kClosParams), *dm = ds.get<float>(kClosParams), *dv = ds.get<float>(kClosParams);
+  float *dsv = ds.get<float>(rows), *dgsv = ds.get<float>(rows), *dl = ds.get<float>(std::max(1, n_steps));
+  if (!dfeat || !dgs || !dgof || !dboff || !dgoff || !dG || !db || !dct || !dp || !dm || !dv || !dsv || !dgsv || !dl)
+    return fail_g(CHFPE_ENOMEM, "closure train scratch");
+  auto up = [&](void *dst, const void *src, size_t bytes) {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st) == hipSuccess;
+  };
+  if (!up(dgs, group_start, (n_groups + 1) * sizeof(int)) || !up(dgof, gof.data(), rows * sizeof(int)) ||
+      !up(dboff, boff.data(), n_groups * sizeof(int)) || !up(dgoff, goff.data(), n_groups * sizeof(long long)) ||
+      !up(dG, G, gtot * sizeof(double)) || !up(db, b, btot * sizeof(double)) ||
+      !up(dct, ct, 2 * n_groups * sizeof(double)) || !up(dp, prm, kClosParams * sizeof(float)) ||
+      !up(dm, adam_m, kClosParams * sizeof(float)) || !up(dv, adam_v, kClosParams * sizeof(float)))
+    return fail_g(CHFPE_EDEVICE, "closure train upload");
+  ClosGroups gr{dgs, dgof, dgoff, dboff, dG, db, dct, n_groups};
+  hipLaunchKernelGGL(k_clos_train, dim3(1), dim3(256), 0, st, dp, dm, dv, (int)adam_t0, dfeat, (int)rows, gr,
+                     (int)n_steps, lr, dsv, dgsv, dl);
+  if (hipGetLastError() != hipSuccess) return fail_g(CHFPE_EDEVICE, "closure train launch");
+  bool ok = hipMemcpyAsync(prm, dp, kClosParams * sizeof(float), hipMemcpyDeviceToHost, st) == hipSuccess &&
+            hipMemcpyAsync(adam_m, dm, kClosParams * sizeof(float), hipMemcpyDeviceToHost, st) == hipSuccess &&
+            hipMemcpyAsync(adam_v, dv, kClosParams * sizeof(float), hipMemcpyDeviceToHost, st) == hipSuccess;
+  if (ok && loss && n_steps > 0)
+    ok = hipMemcpyAsync(loss, dl, n_steps * sizeof(float), hipMemcpyDeviceToHost, st) == hipSuccess;
+  if (!ok || hipStreamSynchronize(st) != hipSuccess) return fail_g(CHFPE_EDEVICE, "closure train copy");
+  return CHFPE_OK;
+}
+
+int chfpe_set_closure(chfpe_ctx *c, const double *sv) {
+  if (!c) return CHFPE_EINVAL;
+  if (!sv) {
+    c->closure_on = false;
+  } else {
+    const Derived &d = c->d;
+    if (d.prec != CHFPE_FP64) return fail(c, CHFPE_EINVAL, "the closure runs with FP64 states only");
+    const int M = d.M;
+    int N[6];
+    double h[6], L[6];
+    axis_table(&c->prm, M, N, h, L);
+    for (int a = 0; a < 2 * M; ++a)
+      if (N[a] > 16) return fail(c, CHFPE_EINVAL, "the closure needs every axis to have at most 16 points");
+    for (int r = 0; r < closure_rows(&c->prm); ++r)
+      if (!std::isfinite(sv[r])) return fail(c, CHFPE_EINVAL, "closure entries must be finite");
+    std::vector<double> tab(6 * 8 * kTab, 0.0);
+    int row = 0;
+    for (int a = 0; a < 2 * M; ++a) {
+      const int n = N[a];
+      std::vector<double> s1(n + 2, 0.0), s2(n + 2, 0.0);  // s1[i]: S[i][i+1], s2[i]: S[i][i+2]
+      for (int i = 0; i < n - 1; ++i) s1[i] = sv[row++];
+      for (int i = 0; i < n - 2; ++i) s2[i] = sv[row++];
+      double *top = &tab[a * 8 * kTab], *mir = top + 4 * kTab;
+      for (int i = 0; i < n; ++i) {
+        const double p1 = (7.0 / 9.0 + s1[i]) / h[a];
+        const double m1 = -(7.0 / 9.0 + (i >= 1 ? s1[i - 1] : 0.0)) / h[a];
+        const double p2 = (1.0 / 36.0 + s2[i]) / h[a];
+        const double m2 = -(1.0 / 36.0 + (i >= 2 ? s2[i - 2] : 0.0)) / h[a];
+        top[i] = p1;
+        top[kTab + i] = m1;
+        top[2 * kTab + i] = p2;
+        top[3 * kTab + i] = m2;
+        // the mirrored line (position j = n - 1 - i) swaps the roles of the
+        // forward and backward neighbours
+        const int j = n - 1 - i;
+        mir[j] = m1;
+        mir[kTab + j] = p1;
+        mir[2 * kTab + j] = m2;
+        mir[3 * kTab + j] = p2;
+      }
+    }
+    HIPCHK(c, hipMemcpyAsync(const_cast<double *>(c->tb.clos), tab.data(), tab.size() * sizeof(double),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->closure_on = true;
+  }
+  if (c->wave_graph) {  // captured with the other kernel variants
+    HIPCHK(c, hipGraphExecDestroy(c->wave_graph));
+    c->wave_graph = nullptr;
+  }
+  return CHFPE_OK;
 }
 
 }  // extern "C"

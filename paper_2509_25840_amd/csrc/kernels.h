@@ -63,13 +63,29 @@ constexpr ThomasTable make_thomas() {
 
 constexpr ThomasTable kThomas = make_thomas();
 
+// Right-hand side of the compact scheme at position i of a line,
+//   (1/3) f'_{i-1} + f'_i + (1/3) f'_{i+1}
+//       = ca (f_{i+1} - f_{i-1}) + cb (f_{i+2} - f_{i-2}),  ca = 7/(9h), cb = 1/(36h),
+// or, with a closure (CLOS), with the per-position weights of a table ct:
+//   p1[i] f_{i+1} + m1[i] f_{i-1} + p2[i] f_{i+2} + m2[i] f_{i-2},
+// rows p1, m1, p2, m2 of kTab entries each.  A closure adds a skew-symmetric
+// band S to the scheme's right-hand side (A y = (B + S) f / h), so the plain
+// weights are p1 = -m1 = ca and p2 = -m2 = cb.
+template <typename T, bool CLOS>
+__device__ __forceinline__ T stencil_rhs(const int i, const T fm2, const T fm1, const T fp1, const T fp2,
+                                         const T ca, const T cb, const double *ct) {
+  if constexpr (CLOS)
+    return T(ct[i]) * fp1 + T(ct[kTab + i]) * fm1 + T(ct[2 * kTab + i]) * fp2 + T(ct[3 * kTab + i]) * fm2;
+  else
+    return ca * (fp1 - fm1) + cb * (fp2 - fm2);
+}
+
 // Compact sixth-order first derivative of one line held in registers.
 // On entry f[0..N) holds the line and f[N..NMAX) must be zero (values beyond
 // the box are zero); on exit f[0..N) holds the derivative.
-//   (1/3) f'_{i-1} + f'_i + (1/3) f'_{i+1}
-//       = ca (f_{i+1} - f_{i-1}) + cb (f_{i+2} - f_{i-2}),  ca = 7/(9h), cb = 1/(36h).
-template <typename T, int NMAX>
-__device__ __forceinline__ void compact_deriv(T (&f)[NMAX], const int N, const T ca, const T cb) {
+template <typename T, int NMAX, bool CLOS = false>
+__device__ __forceinline__ void compact_deriv(T (&f)[NMAX], const int N, const T ca, const T cb,
+                                              const double *ct = nullptr) {
   constexpr T third = T(1.0 / 3.0);
   T d[NMAX];
 #pragma unroll
@@ -79,7 +95,7 @@ __device__ __forceinline__ void compact_deriv(T (&f)[NMAX], const int N, const T
       const T fm2 = (i >= 2) ? f[i >= 2 ? i - 2 : 0] : T(0);
       const T fp1 = (i + 1 < NMAX) ? f[i + 1 < NMAX ? i + 1 : NMAX - 1] : T(0);
       const T fp2 = (i + 2 < NMAX) ? f[i + 2 < NMAX ? i + 2 : NMAX - 1] : T(0);
-      const T r = ca * (fp1 - fm1) + cb * (fp2 - fm2);
+      const T r = stencil_rhs<T, CLOS>(i, fm2, fm1, fp1, fp2, ca, cb, ct);
       if (i == 0)
         d[0] = r;
       else
@@ -98,8 +114,9 @@ __device__ __forceinline__ void compact_deriv(T (&f)[NMAX], const int N, const T
 }
 
 // Same, for a line of exactly N values (no guards; N known at compile time).
-template <typename T, int N>
-__device__ __forceinline__ void compact_deriv_exact(T (&f)[N], const T ca, const T cb) {
+template <typename T, int N, bool CLOS = false>
+__device__ __forceinline__ void compact_deriv_exact(T (&f)[N], const T ca, const T cb,
+                                                    const double *ct = nullptr) {
   constexpr T third = T(1.0 / 3.0);
   T d[N];
 #pragma unroll
@@ -108,7 +125,7 @@ __device__ __forceinline__ void compact_deriv_exact(T (&f)[N], const T ca, const
     const T fm2 = i >= 2 ? f[i >= 2 ? i - 2 : 0] : T(0);
     const T fp1 = i + 1 < N ? f[i + 1 < N ? i + 1 : 0] : T(0);
     const T fp2 = i + 2 < N ? f[i + 2 < N ? i + 2 : 0] : T(0);
-    const T r = ca * (fp1 - fm1) + cb * (fp2 - fm2);
+    const T r = stencil_rhs<T, CLOS>(i, fm2, fm1, fp1, fp2, ca, cb, ct);
     d[i] = i == 0 ? r : (r - third * d[i >= 1 ? i - 1 : 0]) * T(kThomas.inv[i]);
   }
   f[N - 1] = d[N - 1];
@@ -117,27 +134,28 @@ __device__ __forceinline__ void compact_deriv_exact(T (&f)[N], const T ca, const
 }
 
 // Line of N <= NMAX values; takes the unguarded path when N == NMAX.
-template <typename T, int NMAX>
-__device__ __forceinline__ void compact_line(T (&f)[NMAX], const int N, const T ca, const T cb) {
+template <typename T, int NMAX, bool CLOS = false>
+__device__ __forceinline__ void compact_line(T (&f)[NMAX], const int N, const T ca, const T cb,
+                                             const double *ct = nullptr) {
   if (N == NMAX)
-    compact_deriv_exact<T, NMAX>(f, ca, cb);
+    compact_deriv_exact<T, NMAX, CLOS>(f, ca, cb, ct);
   else
-    compact_deriv<T, NMAX>(f, N, ca, cb);
+    compact_deriv<T, NMAX, CLOS>(f, N, ca, cb, ct);
 }
 
 // Same derivative for a line of N values held in LDS at base + i * stride,
 // in place, with O(1) registers: a five-value window of the input moves
 // ahead of the forward sweep, which stores d_i over f_i once f_i is in the
 // window; the backward sweep then overwrites d_i with the result.
-template <typename T>
+template <typename T, bool CLOS = false>
 __device__ __forceinline__ void compact_lds(T *G, const int base, const int stride, const int N, const T ca,
-                                            const T cb) {
+                                            const T cb, const double *ct = nullptr) {
   constexpr T third = T(1.0 / 3.0);
   T fm2 = T(0), fm1 = T(0), f0 = G[base], fp1 = N > 1 ? G[base + stride] : T(0);
   T fp2 = N > 2 ? G[base + 2 * stride] : T(0);
   T dprev = T(0);
   for (int i = 0; i < N; ++i) {
-    const T r = ca * (fp1 - fm1) + cb * (fp2 - fm2);
+    const T r = stencil_rhs<T, CLOS>(i, fm2, fm1, fp1, fp2, ca, cb, ct);
     const T d = i == 0 ? r : (r - third * dprev) * T(kThomas.inv[i]);
     G[base + i * stride] = d;
     dprev = d;
@@ -159,14 +177,15 @@ __device__ __forceinline__ void compact_lds(T *G, const int base, const int stri
 // its own end of the line, the pair couples its last two unknowns through one
 // exchange, and each back-substitutes its half.  tridiag(1/3, 1, 1/3) is
 // persymmetric, so the far half is the same sweep on the mirrored line: the
-// mirror reverses the load order and flips the sign of the stencil (ca, cb),
-// and the coupling of the two last equations
+// mirror reverses the load order and flips the sign of the stencil (ca, cb;
+// a closure table carries its own mirrored rows at ct + 4 kTab), and the
+// coupling of the two last equations
 //   x_{H-1} + c x_H = d_own,  x_H + c x_{H-1} = d_partner  (c = cp_{H-1})
 // gives x_own = (d_own - c d_partner) / (1 - c^2) in either lane.
 // Both lanes of a pair must call this together.
-template <typename T, int N>
+template <typename T, int N, bool CLOS = false>
 __device__ __forceinline__ void compact_split(T *G, const int base, const int stride, const int half,
-                                              T ca, T cb) {
+                                              T ca, T cb, const double *ct = nullptr) {
   static_assert(N % 2 == 0 && N >= 4, "split solve needs an even line of at least 4");
   constexpr int H = N / 2;
   constexpr double cm = kThomas.cp[H - 1];
@@ -177,6 +196,7 @@ __device__ __forceinline__ void compact_split(T *G, const int base, const int st
     ca = -ca;
     cb = -cb;
   }
+  const double *cto = CLOS ? ct + (half ? 4 * kTab : 0) : ct;
   T f[H + 2];
 #pragma unroll
   for (int i = 0; i < H + 2; ++i) f[i] = G[start + i * step];
@@ -185,7 +205,7 @@ __device__ __forceinline__ void compact_split(T *G, const int base, const int st
   for (int i = 0; i < H; ++i) {
     const T fm1 = i >= 1 ? f[i >= 1 ? i - 1 : 0] : T(0);
     const T fm2 = i >= 2 ? f[i >= 2 ? i - 2 : 0] : T(0);
-    const T r = ca * (f[i + 1] - fm1) + cb * (f[i + 2] - fm2);
+    const T r = stencil_rhs<T, CLOS>(i, fm2, fm1, f[i + 1], f[i + 2], ca, cb, cto);
     if (i == 0)
       d[0] = r;
     else  // d_i = (r_i - d_{i-1}/3) / pivot_i, one dependent FMA
@@ -244,6 +264,8 @@ struct Tabs {
   const double *cc;     // [e][s]     n_s zeta_s gamma_s m_s / beta
   const double *tc;     // [e][s]     n_s zeta_s gamma_s
   const double *damp;   // [e]        sum_s n_s gamma_s
+  const double *clos;   // [axis][orientation][4][kTab] closure stencil weights (axis ids
+                        // 0..M-1 q_s, M..2M-1 p_s; orientation 1 = mirrored line)
 };
 
 // Consecutive workgroup ids are dispatched round-robin over the 8 XCDs.
@@ -318,7 +340,7 @@ struct QPass {
 // LDS; (2) row and column lines are solved together; (3) one pass writes out.
 // T: type of X and of the arithmetic; TO: type of out.  A batch of nbatch
 // states is laid out [branch][n][q][p]; tasks cover every (branch, n).
-template <typename T, typename TO, int NMAX, int RPT, int MM, bool PERTURB>
+template <typename T, typename TO, int NMAX, int RPT, int MM, bool PERTURB, bool CLOS = false>
 __global__ void __launch_bounds__(256, (NMAX <= 24 || (NMAX == 32 && MM == 2)) ? 5 : NMAX <= 32 ? 4 : 3)
 k_pblock(const Geom g, const Tabs tb, const PBlock pb, const T *__restrict__ X, TO *__restrict__ out,
          const double *__restrict__ grad) {
@@ -471,14 +493,16 @@ k_pblock(const Geom g, const Tabs tb, const PBlock pb, const T *__restrict__ X, 
       const int lb = l - nla;
       const int blk = lb / NMAX;
       const int base = is_row ? l * cp : blk * NMAX * cp + (lb - blk * NMAX);
-      compact_split<T, NMAX>(is_row ? Ga : Gb, base, is_row ? 1 : cp, hl & 1, is_row ? ca_a : ca_b,
-                             is_row ? cb_a : cb_b);
+      const double *ct = CLOS ? tb.clos + (MM + (is_row ? sa : (NB == 2 ? sb : sa))) * 8 * kTab : nullptr;
+      compact_split<T, NMAX, CLOS>(is_row ? Ga : Gb, base, is_row ? 1 : cp, hl & 1, is_row ? ca_a : ca_b,
+                                   is_row ? cb_a : cb_b, ct);
     }
   } else {
     for (int l = tid; l < nla + nlb; l += blockDim.x) {
       T *G;
       int base, stride, N;
       T ca, cb;
+      const double *ct = nullptr;
       if (l < nla) {
         G = Ga;
         base = l * cp;
@@ -486,6 +510,7 @@ k_pblock(const Geom g, const Tabs tb, const PBlock pb, const T *__restrict__ X, 
         N = cols;
         ca = T(g.dp_ca[sa]);
         cb = T(g.dp_cb[sa]);
+        if (CLOS) ct = tb.clos + (MM + sa) * 8 * kTab;
       } else {
         const int lb = l - nla;
         const int blk = lb / cols;
@@ -496,8 +521,9 @@ k_pblock(const Geom g, const Tabs tb, const PBlock pb, const T *__restrict__ X, 
         N = rows;
         ca = T(g.dp_ca[NB == 2 ? sb : sa]);
         cb = T(g.dp_cb[NB == 2 ? sb : sa]);
+        if (CLOS) ct = tb.clos + (MM + (NB == 2 ? sb : sa)) * 8 * kTab;
       }
-      compact_lds<T>(G, base, stride, N, ca, cb);
+      compact_lds<T, CLOS>(G, base, stride, N, ca, cb, ct);
     }
   }
   __syncthreads();
@@ -550,7 +576,7 @@ __device__ __forceinline__ T field_at(const Geom &g, const Tabs &tb, const T *__
 }
 
 // T: type of X and of the arithmetic; TO: type of Tacc, y, yacc, xo.
-template <typename T, typename TO, int NMAX, bool TWO, int EPI, int FA, int FB>
+template <typename T, typename TO, int NMAX, bool TWO, int EPI, int FA, int FB, bool CLOS = false>
 __global__ void __launch_bounds__(512)
 k_qpass(const Geom g, const Tabs tb, const QPass qp, const T *__restrict__ X, TO *__restrict__ Tacc,
         const TO *__restrict__ y, TO *__restrict__ yacc, TO *__restrict__ xo, const double *__restrict__ grad,
@@ -624,7 +650,7 @@ k_qpass(const Geom g, const Tabs tb, const QPass qp, const T *__restrict__ X, TO
       T h[NMAX];
 #pragma unroll
       for (int i = 0; i < NMAX; ++i) h[i] = (i < Nb) ? lds[ja * rs + i * pc + c] : T(0);
-      compact_line<T, NMAX>(h, Nb, T(qp.ca_b), T(qp.cb_b));
+      compact_line<T, NMAX, CLOS>(h, Nb, T(qp.ca_b), T(qp.cb_b), CLOS ? tb.clos + qp.b * 8 * kTab : nullptr);
 #pragma unroll
       for (int i = 0; i < NMAX; ++i)
         if (i < Nb) lds[ja * rs + i * pc + c] = h[i];
@@ -642,7 +668,7 @@ k_qpass(const Geom g, const Tabs tb, const QPass qp, const T *__restrict__ X, TO
     else
       d[i] = (i < Na) ? field_at<T, FA>(g, tb, Xb, grad, e, qp.sa_mode, lrel + i * qp.sa, f[i]) : T(0);
   }
-  compact_line<T, NMAX>(d, Na, T(qp.ca_a), T(qp.cb_a));
+  compact_line<T, NMAX, CLOS>(d, Na, T(qp.ca_a), T(qp.cb_a), CLOS ? tb.clos + qp.a * 8 * kTab : nullptr);
 
   // coefficients: -p_s/m_s for q-type axes (p_s is fixed along the line)
   int ql0, pix0;
