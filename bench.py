@@ -349,8 +349,18 @@ def main(argv=None):
         args.batch = 1  # propagation of one FP64 state: no branch buffers
     elif args.batch <= 0:
         args.batch = auto_batch(pk, w, prec, torch.cuda.get_device_properties(0).total_memory)
-    solver = pk.Solver(pk.params_from_workload(w, precision=prec, batch=args.batch))
-    S = solver.count
+    if args.mode in ("precision", "closure"):
+        # these modes make their own contexts; no workspace of this shape
+        S = wl.n_elements(int(w["M"]), int(w["K"])) * int(np.prod(w["Nq"])) * int(np.prod(w["Np"]))
+
+        class _NoSolver:
+            def close(self):
+                pass
+
+        solver = _NoSolver()
+    else:
+        solver = pk.Solver(pk.params_from_workload(w, precision=prec, batch=args.batch))
+        S = solver.count
     log(f"[bench] workload={args.workload} values/state={S} rk4_steps/step={steps_per}")
 
     if args.mode == "rk4":

@@ -238,20 +238,19 @@ int chfpe_tile_config(const chfpe_ctx *ctx, int32_t *out, int32_t n);
  * one grid.  A closure lets a coarse grid (half the points per axis of a fine
  * grid on the same box) stand in for the fine one: along each grid axis a,
  * the compact system A y = B f / h becomes A y = (B + S_a) f / h, with S_a
- * skew-symmetric on the first two off-diagonals (S[i][i+k] = -S[i+k][i] = s,
- * k = 1, 2), which keeps A D skew like the plain scheme.  The entries s are
+ * skew-symmetric on the first two off-diagonals (S[i][i+k] = -S[i+k][i] =
+ * s, k = 1, 2), which keeps A D skew like the plain scheme.  The entries s are
  * the output of a network of one hidden layer (16 features -> 32 tanh units
  * -> 1; BF16 weights and activations in MFMA products, FP32 accumulation),
  * trained on this device against fine-grid states of the solver itself.
  * Rows of the network: one per (axis, entry), axes in id order (q_1..q_M,
- * p_1..p_M), entries S[i][i+1] for i < N_a - 1, then S[i][i+2] for
- * i < N_a - 2.  Parameters (FP32, 577): W1[16][32], b1[32], W2[32], b2. */
+ * p_1..p_M), entries S[i][i+k] for k = 1, 2 in turn, i < N_a - k.  Parameters (FP32, 577): W1[16][32], b1[32], W2[32], b2. */
 
 /* Number of rows, sum over axes of 2 N_a - 3; EINVAL for invalid params. */
 int32_t chfpe_closure_rows(const chfpe_params *coarse);
 
-/* Features of every row (host, rows x 16 FP32): u, u^2, |u| (u: the entry's
- * midpoint over the half box), [k == 2], [p axis], h / sigma (sigma: thermal
+/* Features of every row (host, rows x 16 FP32): u, u^2 (u: the entry's
+ * midpoint over the half box), |u|, [k == 2], [p axis], h / sigma (sigma: thermal
  * width, 1/(omega sqrt(beta m)) for q, sqrt(m/beta) for p), omega/1.6,
  * g3 sigma_q/(m omega^2), g4 sigma_q^2/(m omega^2), V_SL sigma_q / V_LL,
  * zeta, gamma, beta/2, m, [entry touches the box edge], 1.  axis_of_row

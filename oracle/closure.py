@@ -3,15 +3,17 @@
 Only ``tests/`` and the smoke check may import this module; the HIP library
 never calls it.  It shares no code with the HIP path.
 
-The paper computes on one grid and mentions machine learning only as an
-outlook, so the closure is a reading of this project (listed with the other
-readings in the design notes):
+The paper computes on one grid and mentions machine learning only for
+extracting model parameters from MD trajectories (Sec. V), so the closure is
+a reading of this project (listed with the other readings in the design
+notes):
 
 * Closure form.  On a coarse grid, the compact first derivative of
   Sec. III B along grid axis a solves A y = (B + S_a) f / h_a instead of
   A y = B f / h_a.  S_a is skew-symmetric with nonzero entries only on the
-  first two off-diagonals: S[i, i+1] = -S[i+1, i] = s1[i] (i < N-1) and
-  S[i, i+2] = -S[i+2, i] = s2[i] (i < N-2), so P = 2N - 3 numbers per axis.
+  first two off-diagonals: S[i, i+k] = -S[i+k, i] (k = 1, 2, i < N - k),
+  so P = 2N - 3 numbers per axis.  (A third off-diagonal fits the training
+  derivatives better but gave larger spectrum errors on held-out draws.)
   Skew-symmetry keeps A D skew, as for the plain scheme (A symmetric, B
   skew), which keeps the generator stable; an unconstrained banded stencil
   fitted to the same data is not.
@@ -39,6 +41,7 @@ from . import dense
 
 NFEAT = 16
 NHID = 32
+KMAX = 2  # off-diagonals of the skew correction
 
 
 # ---------------------------------------------------------------------------
@@ -46,8 +49,12 @@ NHID = 32
 # ---------------------------------------------------------------------------
 def skew_entries(N: int):
     """(i, k) of the free entries S[i, i+k]: k = 1 for i < N-1, then k = 2
-    for i < N-2 (this order is the order of s)."""
-    return [(i, 1) for i in range(N - 1)] + [(i, 2) for i in range(N - 2)]
+    for i < N-2, and so on up to KMAX (this order is the order of s)."""
+    return [(i, k) for k in range(1, KMAX + 1) for i in range(N - k)]
+
+
+def n_entries(N: int) -> int:
+    return sum(N - k for k in range(1, KMAX + 1))
 
 
 def skew_matrix(N: int, s) -> np.ndarray:
@@ -114,7 +121,8 @@ def gram(N: int, h: float, Mx: np.ndarray, Cxr: np.ndarray):
     A, _ = dense.compact_matrices(N)
     Ai = np.linalg.inv(A)
     K = Ai.T @ Ai
-    E = [skew_matrix(N, np.eye(2 * N - 3)[e]) for e in range(2 * N - 3)]
+    P = n_entries(N)
+    E = [skew_matrix(N, np.eye(P)[e]) for e in range(P)]
     P = len(E)
     G = np.empty((P, P))
     b = np.empty(P)
@@ -161,7 +169,7 @@ def features(w_coarse: dict) -> np.ndarray:
 
 def row_axes(w_coarse: dict) -> np.ndarray:
     N, _, _ = axis_lengths(w_coarse)
-    return np.concatenate([np.full(2 * N[a] - 3, a) for a in range(2 * w_coarse["M"])])
+    return np.concatenate([np.full(n_entries(N[a]), a) for a in range(2 * w_coarse["M"])])
 
 
 # ---------------------------------------------------------------------------
@@ -243,7 +251,7 @@ def split_rows(w_coarse: dict, s):
     N, _, _ = axis_lengths(w_coarse)
     out, o = [], 0
     for a in range(2 * w_coarse["M"]):
-        P = 2 * N[a] - 3
+        P = n_entries(N[a])
         out.append(np.asarray(s[o:o + P], dtype=np.float64))
         o += P
     return out

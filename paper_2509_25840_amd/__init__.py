@@ -419,7 +419,7 @@ class Solver:
         (list of G_a, list of b_a, array of (c_a, t_a)) for the 2:1 coarse grid."""
         M = int(self.params.M)
         N = [int(self.params.Nq[s]) // 2 for s in range(M)] + [int(self.params.Np[s]) // 2 for s in range(M)]
-        P = [2 * n - 3 for n in N]
+        P = [2 * n - 3 for n in N]  # skew entries on two off-diagonals
         G = np.zeros(sum(p * p for p in P))
         b = np.zeros(sum(P))
         ct = np.zeros(2 * 2 * M)

@@ -201,7 +201,7 @@ Layout layout(const Derived &d) {
   L.partial = take(sizeof(double) * kPartials);
   L.scal = take(sizeof(double) * 16);
   L.flag = take(sizeof(int) * 16);
-  L.clos = take(sizeof(double) * 6 * 8 * kTab);  // closure stencil weights, [axis][orientation][4][kTab]
+  L.clos = take(sizeof(double) * 6 * 2 * kClosRows * kTab);  // closure weights [axis][orientation][6][kTab]
   for (int i = 0; i < 7; ++i) L.bufs[i] = take(sizeof(double) * (size_t)d.S);
   const size_t tsz = d.prec == CHFPE_FP32 ? sizeof(float) : sizeof(double);
   for (int i = 0; i < 5; ++i) L.bbufs[i] = d.batched ? take(tsz * (size_t)d.S * d.B) : 0;
@@ -1143,10 +1143,11 @@ struct DevScratch {
 };
 
 // Rows of the closure network for a coarse problem: one per (axis, skew
-// entry), axes in id order, entries S[i][i+1] (i < N-1) then S[i][i+2].
+// entry), axes in id order, entries S[i][i+k] for k = 1 .. kClosBands
+// (i < N - k).
 int closure_rows(const chfpe_params *p) {
   int n = 0;
-  for (int a = 0; a < 2 * p->M; ++a) n += 2 * (a < p->M ? p->Nq[a % p->M] : p->Np[a % p->M]) - 3;
+  for (int a = 0; a < 2 * p->M; ++a) n += skew_entries(a < p->M ? p->Nq[a % p->M] : p->Np[a % p->M]);
   return n;
 }
 
@@ -1672,9 +1673,12 @@ int chfpe_closure_features(const chfpe_params *p, float *feat, int32_t *axis_of_
     const double m = p->m[s], om = p->omega[s], beta = p->beta;
     const double sig_q = 1.0 / (om * std::sqrt(beta * m));
     const double sig = a < M ? sig_q : std::sqrt(m / beta);
-    for (int e = 0; e < 2 * N[a] - 3; ++e) {
-      const int k = e < N[a] - 1 ? 1 : 2;
-      const int i = e < N[a] - 1 ? e : e - (N[a] - 1);
+    for (int e = 0; e < skew_entries(N[a]); ++e) {
+      int k = 1, i = e;
+      while (i >= N[a] - k) {
+        i -= N[a] - k;
+        ++k;
+      }
       const double xi = -L[a] + (i + 0.5) * h[a], xk = -L[a] + (i + k + 0.5) * h[a];
       const double u = 0.5 * (xi + xk) / L[a];
       const int edge = std::min(i, N[a] - 1 - (i + k));
@@ -1727,7 +1731,7 @@ int chfpe_closure_moments(chfpe_ctx *c, double *G, double *b, double *ct) {
   DevScratch ds;
   size_t goff = 0, boff = 0;
   for (int a = 0; a < nd; ++a) {
-    const int N = Nc[a], P = 2 * N - 3;
+    const int N = Nc[a], P = skew_entries(N);
     const double hc = 2.0 * hf[a];
     // target T = R(D_fine y) and residual r = T - D_coarse x
     launch_axis_deriv(c->stream, c->y, c->t, nullptr, 1.0, axis_lines(Nf, nd, a, ne), hf[a]);
@@ -1883,30 +1887,30 @@ int chfpe_set_closure(chfpe_ctx *c, const double *sv) {
       if (N[a] > 16) return fail(c, CHFPE_EINVAL, "the closure needs every axis to have at most 16 points");
     for (int r = 0; r < closure_rows(&c->prm); ++r)
       if (!std::isfinite(sv[r])) return fail(c, CHFPE_EINVAL, "closure entries must be finite");
-    std::vector<double> tab(6 * 8 * kTab, 0.0);
+    std::vector<double> tab(6 * 2 * kClosRows * kTab, 0.0);
     int row = 0;
     for (int a = 0; a < 2 * M; ++a) {
       const int n = N[a];
-      std::vector<double> s1(n + 2, 0.0), s2(n + 2, 0.0);  // s1[i]: S[i][i+1], s2[i]: S[i][i+2]
-      for (int i = 0; i < n - 1; ++i) s1[i] = sv[row++];
-      for (int i = 0; i < n - 2; ++i) s2[i] = sv[row++];
-      double *top = &tab[a * 8 * kTab], *mir = top + 4 * kTab;
+      // sk[k][i] = S[i][i+k]; zero where i + k is outside the line
+      std::vector<double> sk[4];
+      for (int k = 1; k <= 3; ++k) {
+        sk[k].assign(n + 4, 0.0);
+        if (k <= kClosBands)
+          for (int i = 0; i < n - k; ++i) sk[k][i] = sv[row++];
+      }
+      const double base[4] = {0.0, 7.0 / 9.0, 1.0 / 36.0, 0.0};  // plain weights of f_{i+k} - f_{i-k}
+      double *top = &tab[a * 2 * kClosRows * kTab], *mir = top + kClosRows * kTab;
       for (int i = 0; i < n; ++i) {
-        const double p1 = (7.0 / 9.0 + s1[i]) / h[a];
-        const double m1 = -(7.0 / 9.0 + (i >= 1 ? s1[i - 1] : 0.0)) / h[a];
-        const double p2 = (1.0 / 36.0 + s2[i]) / h[a];
-        const double m2 = -(1.0 / 36.0 + (i >= 2 ? s2[i - 2] : 0.0)) / h[a];
-        top[i] = p1;
-        top[kTab + i] = m1;
-        top[2 * kTab + i] = p2;
-        top[3 * kTab + i] = m2;
-        // the mirrored line (position j = n - 1 - i) swaps the roles of the
-        // forward and backward neighbours
-        const int j = n - 1 - i;
-        mir[j] = m1;
-        mir[kTab + j] = p1;
-        mir[2 * kTab + j] = m2;
-        mir[3 * kTab + j] = p2;
+        const int j = n - 1 - i;  // position on the mirrored line
+        for (int k = 1; k <= 3; ++k) {
+          const double pk = (base[k] + sk[k][i]) / h[a];                      // weight of f_{i+k}
+          const double mk = -(base[k] + (i >= k ? sk[k][i - k] : 0.0)) / h[a];  // weight of f_{i-k}
+          top[(2 * k - 2) * kTab + i] = pk;
+          top[(2 * k - 1) * kTab + i] = mk;
+          // the mirrored line swaps the roles of the forward and backward neighbours
+          mir[(2 * k - 2) * kTab + j] = mk;
+          mir[(2 * k - 1) * kTab + j] = pk;
+        }
       }
     }
     HIPCHK(c, hipMemcpyAsync(const_cast<double *>(c->tb.clos), tab.data(), tab.size() * sizeof(double),

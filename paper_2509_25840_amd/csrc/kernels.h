@@ -67,15 +67,17 @@ constexpr ThomasTable kThomas = make_thomas();
 //   (1/3) f'_{i-1} + f'_i + (1/3) f'_{i+1}
 //       = ca (f_{i+1} - f_{i-1}) + cb (f_{i+2} - f_{i-2}),  ca = 7/(9h), cb = 1/(36h),
 // or, with a closure (CLOS), with the per-position weights of a table ct:
-//   p1[i] f_{i+1} + m1[i] f_{i-1} + p2[i] f_{i+2} + m2[i] f_{i-2},
-// rows p1, m1, p2, m2 of kTab entries each.  A closure adds a skew-symmetric
-// band S to the scheme's right-hand side (A y = (B + S) f / h), so the plain
-// weights are p1 = -m1 = ca and p2 = -m2 = cb.
+//   sum_{k=1..3} pk[i] f_{i+k} + mk[i] f_{i-k},
+// rows p1, m1, p2, m2, p3, m3 of kTab entries each.  A closure adds a
+// skew-symmetric band S to the scheme's right-hand side (A y = (B + S) f / h),
+// so the plain weights are p1 = -m1 = ca, p2 = -m2 = cb, p3 = m3 = 0.
+constexpr int kClosRows = 6;  // table rows per orientation
 template <typename T, bool CLOS>
-__device__ __forceinline__ T stencil_rhs(const int i, const T fm2, const T fm1, const T fp1, const T fp2,
-                                         const T ca, const T cb, const double *ct) {
+__device__ __forceinline__ T stencil_rhs(const int i, const T fm3, const T fm2, const T fm1, const T fp1,
+                                         const T fp2, const T fp3, const T ca, const T cb, const double *ct) {
   if constexpr (CLOS)
-    return T(ct[i]) * fp1 + T(ct[kTab + i]) * fm1 + T(ct[2 * kTab + i]) * fp2 + T(ct[3 * kTab + i]) * fm2;
+    return T(ct[i]) * fp1 + T(ct[kTab + i]) * fm1 + T(ct[2 * kTab + i]) * fp2 + T(ct[3 * kTab + i]) * fm2 +
+           T(ct[4 * kTab + i]) * fp3 + T(ct[5 * kTab + i]) * fm3;
   else
     return ca * (fp1 - fm1) + cb * (fp2 - fm2);
 }
@@ -93,9 +95,11 @@ __device__ __forceinline__ void compact_deriv(T (&f)[NMAX], const int N, const T
     if (i < N) {
       const T fm1 = (i >= 1) ? f[i >= 1 ? i - 1 : 0] : T(0);
       const T fm2 = (i >= 2) ? f[i >= 2 ? i - 2 : 0] : T(0);
+      const T fm3 = (i >= 3) ? f[i >= 3 ? i - 3 : 0] : T(0);
       const T fp1 = (i + 1 < NMAX) ? f[i + 1 < NMAX ? i + 1 : NMAX - 1] : T(0);
       const T fp2 = (i + 2 < NMAX) ? f[i + 2 < NMAX ? i + 2 : NMAX - 1] : T(0);
-      const T r = stencil_rhs<T, CLOS>(i, fm2, fm1, fp1, fp2, ca, cb, ct);
+      const T fp3 = (i + 3 < NMAX) ? f[i + 3 < NMAX ? i + 3 : NMAX - 1] : T(0);
+      const T r = stencil_rhs<T, CLOS>(i, fm3, fm2, fm1, fp1, fp2, fp3, ca, cb, ct);
       if (i == 0)
         d[0] = r;
       else
@@ -123,9 +127,11 @@ __device__ __forceinline__ void compact_deriv_exact(T (&f)[N], const T ca, const
   for (int i = 0; i < N; ++i) {
     const T fm1 = i >= 1 ? f[i >= 1 ? i - 1 : 0] : T(0);
     const T fm2 = i >= 2 ? f[i >= 2 ? i - 2 : 0] : T(0);
+    const T fm3 = i >= 3 ? f[i >= 3 ? i - 3 : 0] : T(0);
     const T fp1 = i + 1 < N ? f[i + 1 < N ? i + 1 : 0] : T(0);
     const T fp2 = i + 2 < N ? f[i + 2 < N ? i + 2 : 0] : T(0);
-    const T r = stencil_rhs<T, CLOS>(i, fm2, fm1, fp1, fp2, ca, cb, ct);
+    const T fp3 = i + 3 < N ? f[i + 3 < N ? i + 3 : 0] : T(0);
+    const T r = stencil_rhs<T, CLOS>(i, fm3, fm2, fm1, fp1, fp2, fp3, ca, cb, ct);
     d[i] = i == 0 ? r : (r - third * d[i >= 1 ? i - 1 : 0]) * T(kThomas.inv[i]);
   }
   f[N - 1] = d[N - 1];
@@ -144,26 +150,29 @@ __device__ __forceinline__ void compact_line(T (&f)[NMAX], const int N, const T 
 }
 
 // Same derivative for a line of N values held in LDS at base + i * stride,
-// in place, with O(1) registers: a five-value window of the input moves
+// in place, with O(1) registers: a seven-value window of the input moves
 // ahead of the forward sweep, which stores d_i over f_i once f_i is in the
 // window; the backward sweep then overwrites d_i with the result.
 template <typename T, bool CLOS = false>
 __device__ __forceinline__ void compact_lds(T *G, const int base, const int stride, const int N, const T ca,
                                             const T cb, const double *ct = nullptr) {
   constexpr T third = T(1.0 / 3.0);
-  T fm2 = T(0), fm1 = T(0), f0 = G[base], fp1 = N > 1 ? G[base + stride] : T(0);
+  T fm3 = T(0), fm2 = T(0), fm1 = T(0), f0 = G[base], fp1 = N > 1 ? G[base + stride] : T(0);
   T fp2 = N > 2 ? G[base + 2 * stride] : T(0);
+  T fp3 = N > 3 ? G[base + 3 * stride] : T(0);
   T dprev = T(0);
   for (int i = 0; i < N; ++i) {
-    const T r = stencil_rhs<T, CLOS>(i, fm2, fm1, fp1, fp2, ca, cb, ct);
+    const T r = stencil_rhs<T, CLOS>(i, fm3, fm2, fm1, fp1, fp2, fp3, ca, cb, ct);
     const T d = i == 0 ? r : (r - third * dprev) * T(kThomas.inv[i]);
     G[base + i * stride] = d;
     dprev = d;
+    fm3 = fm2;
     fm2 = fm1;
     fm1 = f0;
     f0 = fp1;
     fp1 = fp2;
-    fp2 = (i + 3 < N) ? G[base + (i + 3) * stride] : T(0);
+    fp2 = fp3;
+    fp3 = (i + 4 < N) ? G[base + (i + 4) * stride] : T(0);
   }
   T y = dprev;
   for (int i = N - 2; i >= 0; --i) {
@@ -178,7 +187,7 @@ __device__ __forceinline__ void compact_lds(T *G, const int base, const int stri
 // exchange, and each back-substitutes its half.  tridiag(1/3, 1, 1/3) is
 // persymmetric, so the far half is the same sweep on the mirrored line: the
 // mirror reverses the load order and flips the sign of the stencil (ca, cb;
-// a closure table carries its own mirrored rows at ct + 4 kTab), and the
+// a closure table carries its own mirrored rows at ct + kClosRows kTab), and the
 // coupling of the two last equations
 //   x_{H-1} + c x_H = d_own,  x_H + c x_{H-1} = d_partner  (c = cp_{H-1})
 // gives x_own = (d_own - c d_partner) / (1 - c^2) in either lane.
@@ -186,7 +195,7 @@ __device__ __forceinline__ void compact_lds(T *G, const int base, const int stri
 template <typename T, int N, bool CLOS = false>
 __device__ __forceinline__ void compact_split(T *G, const int base, const int stride, const int half,
                                               T ca, T cb, const double *ct = nullptr) {
-  static_assert(N % 2 == 0 && N >= 4, "split solve needs an even line of at least 4");
+  static_assert(N % 2 == 0 && N >= 6, "split solve needs an even line of at least 6");
   constexpr int H = N / 2;
   constexpr double cm = kThomas.cp[H - 1];
   constexpr double inv1mc2 = 1.0 / (1.0 - cm * cm);
@@ -196,16 +205,19 @@ __device__ __forceinline__ void compact_split(T *G, const int base, const int st
     ca = -ca;
     cb = -cb;
   }
-  const double *cto = CLOS ? ct + (half ? 4 * kTab : 0) : ct;
-  T f[H + 2];
+  const double *cto = CLOS ? ct + (half ? kClosRows * kTab : 0) : ct;
+  constexpr int NL = CLOS ? H + 3 : H + 2;  // values this lane reads
+  T f[NL];
 #pragma unroll
-  for (int i = 0; i < H + 2; ++i) f[i] = G[start + i * step];
+  for (int i = 0; i < NL; ++i) f[i] = G[start + i * step];
   T d[H];
 #pragma unroll
   for (int i = 0; i < H; ++i) {
     const T fm1 = i >= 1 ? f[i >= 1 ? i - 1 : 0] : T(0);
     const T fm2 = i >= 2 ? f[i >= 2 ? i - 2 : 0] : T(0);
-    const T r = stencil_rhs<T, CLOS>(i, fm2, fm1, f[i + 1], f[i + 2], ca, cb, cto);
+    const T fm3 = (CLOS && i >= 3) ? f[i >= 3 ? i - 3 : 0] : T(0);
+    const T fp3 = CLOS ? f[i + 3 < NL ? i + 3 : NL - 1] : T(0);
+    const T r = stencil_rhs<T, CLOS>(i, fm3, fm2, fm1, f[i + 1], f[i + 2], fp3, ca, cb, cto);
     if (i == 0)
       d[0] = r;
     else  // d_i = (r_i - d_{i-1}/3) / pivot_i, one dependent FMA
@@ -264,7 +276,7 @@ struct Tabs {
   const double *cc;     // [e][s]     n_s zeta_s gamma_s m_s / beta
   const double *tc;     // [e][s]     n_s zeta_s gamma_s
   const double *damp;   // [e]        sum_s n_s gamma_s
-  const double *clos;   // [axis][orientation][4][kTab] closure stencil weights (axis ids
+  const double *clos;   // [axis][orientation][6][kTab] closure stencil weights (axis ids
                         // 0..M-1 q_s, M..2M-1 p_s; orientation 1 = mirrored line)
 };
 
@@ -493,7 +505,7 @@ k_pblock(const Geom g, const Tabs tb, const PBlock pb, const T *__restrict__ X, 
       const int lb = l - nla;
       const int blk = lb / NMAX;
       const int base = is_row ? l * cp : blk * NMAX * cp + (lb - blk * NMAX);
-      const double *ct = CLOS ? tb.clos + (MM + (is_row ? sa : (NB == 2 ? sb : sa))) * 8 * kTab : nullptr;
+      const double *ct = CLOS ? tb.clos + (MM + (is_row ? sa : (NB == 2 ? sb : sa))) * 2 * kClosRows * kTab : nullptr;
       compact_split<T, NMAX, CLOS>(is_row ? Ga : Gb, base, is_row ? 1 : cp, hl & 1, is_row ? ca_a : ca_b,
                                    is_row ? cb_a : cb_b, ct);
     }
@@ -510,7 +522,7 @@ k_pblock(const Geom g, const Tabs tb, const PBlock pb, const T *__restrict__ X, 
         N = cols;
         ca = T(g.dp_ca[sa]);
         cb = T(g.dp_cb[sa]);
-        if (CLOS) ct = tb.clos + (MM + sa) * 8 * kTab;
+        if (CLOS) ct = tb.clos + (MM + sa) * 2 * kClosRows * kTab;
       } else {
         const int lb = l - nla;
         const int blk = lb / cols;
@@ -521,7 +533,7 @@ k_pblock(const Geom g, const Tabs tb, const PBlock pb, const T *__restrict__ X, 
         N = rows;
         ca = T(g.dp_ca[NB == 2 ? sb : sa]);
         cb = T(g.dp_cb[NB == 2 ? sb : sa]);
-        if (CLOS) ct = tb.clos + (MM + (NB == 2 ? sb : sa)) * 8 * kTab;
+        if (CLOS) ct = tb.clos + (MM + (NB == 2 ? sb : sa)) * 2 * kClosRows * kTab;
       }
       compact_lds<T, CLOS>(G, base, stride, N, ca, cb, ct);
     }
@@ -650,7 +662,7 @@ k_qpass(const Geom g, const Tabs tb, const QPass qp, const T *__restrict__ X, TO
       T h[NMAX];
 #pragma unroll
       for (int i = 0; i < NMAX; ++i) h[i] = (i < Nb) ? lds[ja * rs + i * pc + c] : T(0);
-      compact_line<T, NMAX, CLOS>(h, Nb, T(qp.ca_b), T(qp.cb_b), CLOS ? tb.clos + qp.b * 8 * kTab : nullptr);
+      compact_line<T, NMAX, CLOS>(h, Nb, T(qp.ca_b), T(qp.cb_b), CLOS ? tb.clos + qp.b * 2 * kClosRows * kTab : nullptr);
 #pragma unroll
       for (int i = 0; i < NMAX; ++i)
         if (i < Nb) lds[ja * rs + i * pc + c] = h[i];
@@ -668,7 +680,7 @@ k_qpass(const Geom g, const Tabs tb, const QPass qp, const T *__restrict__ X, TO
     else
       d[i] = (i < Na) ? field_at<T, FA>(g, tb, Xb, grad, e, qp.sa_mode, lrel + i * qp.sa, f[i]) : T(0);
   }
-  compact_line<T, NMAX, CLOS>(d, Na, T(qp.ca_a), T(qp.cb_a), CLOS ? tb.clos + qp.a * 8 * kTab : nullptr);
+  compact_line<T, NMAX, CLOS>(d, Na, T(qp.ca_a), T(qp.cb_a), CLOS ? tb.clos + qp.a * 2 * kClosRows * kTab : nullptr);
 
   // coefficients: -p_s/m_s for q-type axes (p_s is fixed along the line)
   int ql0, pix0;

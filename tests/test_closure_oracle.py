@@ -28,12 +28,12 @@ def test_restriction_is_exact_for_linear_functions():
 
 def test_corrected_derivative_keeps_the_skew_structure():
     N, h = 12, 0.5
-    s = np.random.default_rng(1).normal(0, 0.1, 2 * N - 3)
+    s = np.random.default_rng(1).normal(0, 0.1, cl.n_entries(N))
     A, B = dn.compact_matrices(N)
     D = cl.closure_derivative_matrix(N, h, s)
     X = A @ D * h
     assert np.abs((X + X.T)).max() < 1e-13          # A D h = B + S is skew
-    assert np.allclose(cl.closure_derivative_matrix(N, h, np.zeros(2 * N - 3)),
+    assert np.allclose(cl.closure_derivative_matrix(N, h, np.zeros(cl.n_entries(N))),
                        dn.derivative_matrix(N, h), atol=1e-14)
 
 
@@ -47,7 +47,7 @@ def test_gram_from_moments_matches_explicit_lines():
     X, Rr = _lines(2, N)
     G, b = cl.gram(N, h, X @ X.T, X @ Rr.T)
     A, _ = dn.compact_matrices(N)
-    P = 2 * N - 3
+    P = cl.n_entries(N)
     Gb = np.zeros((P, P))
     bb = np.zeros(P)
     for col in range(X.shape[1]):
@@ -63,7 +63,7 @@ def test_quadratic_loss_equals_the_residual_it_models():
     N, h = 7, 0.8
     X, Rr = _lines(3, N)
     G, b = cl.gram(N, h, X @ X.T, X @ Rr.T)
-    s = np.random.default_rng(4).normal(0, 0.2, 2 * N - 3)
+    s = np.random.default_rng(4).normal(0, 0.2, cl.n_entries(N))
     corr = (cl.closure_derivative_matrix(N, h, s) - dn.derivative_matrix(N, h)) @ X
     direct = float(((Rr - corr) ** 2).sum())
     assert abs(cl.group_loss(s, G, b, float((Rr ** 2).sum()), 1.0) - direct) < 1e-10 * direct
@@ -73,7 +73,7 @@ def test_planted_closure_is_recovered_by_least_squares():
     # targets made by a known closure: the quadratic's minimiser is that closure
     N, h = 8, 0.5
     rng = np.random.default_rng(5)
-    s_true = rng.normal(0, 0.05, 2 * N - 3)
+    s_true = rng.normal(0, 0.05, cl.n_entries(N))
     X = rng.standard_normal((N, 200))
     Rr = (cl.closure_derivative_matrix(N, h, s_true) - dn.derivative_matrix(N, h)) @ X
     G, b = cl.gram(N, h, X @ X.T, X @ Rr.T)
@@ -147,5 +147,8 @@ def test_features_follow_the_definition():
     # first row: q_1 entry S[0][1], midpoint between the first two cells
     L, h = w["Lq"][0], 2 * w["Lq"][0] / 8
     u = (-L + h) / L
-    assert np.isclose(F[0, 0], u) and F[0, 3] == 0.0 and F[0, 4] == 0.0 and F[0, 14] == 1.0
+    assert np.isclose(F[0, 0], u) and np.isclose(F[0, 2], abs(u)) and F[0, 3] == 0.0 and F[0, 4] == 0.0
+    assert F[0, 14] == 1.0
+    # rows 7.. are S[i][i+2]
+    assert F[7, 3] == 1.0 and F[6, 3] == 0.0
     assert np.allclose(cl.row_axes(w), np.repeat(np.arange(4), 13))

@@ -209,3 +209,37 @@ def test_closure_response_2d_matches_the_oracle(pk):
             s.equilibrate(10, 0.004)
             got = s.response_2d(A, B, C, 4, 5, 2, 2, 0.004)
         assert rel(got, ref) < 1e-10, batch
+
+
+def test_trained_closure_beats_the_plain_coarse_grid(pk):
+    """Ablation, in the configuration bench.py --mode closure runs: a closure
+    trained on fine 32^4 runs of sixteen seeded draws brings the 16^4 coarse
+    2D spectrum of the nominal workload (not a training draw) closer to the
+    fine FP64 spectrum than the plain coarse grid, over the full 64 x 256
+    response after full equilibration."""
+    import paper_2509_25840_amd.closure as clo
+    w = wl.workload("two_mode_32")
+    wc = copy.deepcopy(w)
+    wc["Nq"], wc["Np"] = [16, 16], [16, 16]
+    dt = w["dt"]
+    draws = []
+    for sd in range(16):
+        wd = wl.draw_perturbed(wc, sd)
+        draws.append((wd, clo.fine_moments(wd, 1000, 400, 50, dt)))
+    tr, hist = clo.train(clo.training_set(draws), 3000, 3e-3)
+    say(f"    loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+    assert hist[-1] < 0.5 * hist[0]
+
+    def spectrum(wk, sv=None):
+        with pk.Solver(pk.params_from_workload(wk, batch=64)) as s:
+            if sv is not None:
+                s.set_closure(sv)
+            s.equilibrate(w["eq_steps"], dt)
+            R = s.response_2d(wk["A"], wk["B"], wk["C"], w["n_t1"], w["n_t2"], 1, 1, dt)
+        return pk.spectrum_2d(R, dt, dt)
+
+    I_fine = spectrum(clo.fine_of(wc))
+    e_plain = rel(spectrum(wc), I_fine)
+    e_clos = rel(spectrum(wc, clo.entries(tr.prm, wc)), I_fine)
+    say(f"    spectrum error plain {e_plain:.3e} closure {e_clos:.3e}")
+    assert e_clos < 0.5 * e_plain
