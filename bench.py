@@ -461,8 +461,17 @@ def main(argv=None):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             s.equilibrate(int(w["eq_steps"]), dt)
-            R = s.response_2d(w["A"], w["B"], w["C"], int(w["n_t1"]), int(w["n_t2"]),
-                              int(w["stride1"]), int(w["stride2"]), dt)
+            torch.cuda.synchronize()
+            log(f"[precision] {prec_name}: equilibrated ({time.perf_counter() - t0:.1f} s)")
+            # one wave of t1 columns per call, so that progress shows between calls
+            n1 = int(w["n_t1"])
+            cols = []
+            for j0 in range(0, n1, nb):
+                cols.append(s.response_2d_range(w["A"], w["B"], w["C"], j0, min(n1, j0 + nb), int(w["n_t2"]),
+                                                int(w["stride1"]), int(w["stride2"]), dt))
+                log(f"[precision] {prec_name}: t1 columns {j0}..{min(n1, j0 + nb) - 1} "
+                    f"({time.perf_counter() - t0:.1f} s)")
+            R = np.concatenate(cols, axis=1)
             I = pk.spectrum_2d(R, int(w["stride1"]) * dt, int(w["stride2"]) * dt)
             torch.cuda.synchronize()
             el = time.perf_counter() - t0

@@ -65,7 +65,8 @@ enum { CHFPE_FP64 = 0, CHFPE_FP32 = 1 };
  *     with batch > 1 or CHFPE_FP32, branches run in waves of `batch` states
  *     (batch x 5 extra state buffers of the branch type in the workspace),
  *     each wave's t2 loop as one captured HIP graph.
- * Limits: 1 <= M <= 3, 0 <= K <= 12, 5 <= N <= 48 on every axis, all
+ * Limits: 1 <= M <= 3, 0 <= K <= 12, 5 <= N <= 48 on every axis (the last
+ * two p axes also within the tiling limit under chfpe_setup), all
  * masses, beta, L > 0, one element below 2^29 points, and
  * exp(-beta H_sys/2) representable (> 1e-150) everywhere on the grid.
  */
@@ -115,8 +116,15 @@ size_t chfpe_workspace_bytes(const chfpe_params *p);
  *   hip_stream: a hipStream_t on the current device, or NULL for the null
  *     stream.
  *   out: receives the new context; untouched on error.
- * Errors: EINVAL (bad parameters), ENOMEM (workspace too small or allocation
- * failed), EDEVICE. */
+ * Errors: EINVAL (bad parameters; also a grid the p-block tile cannot cover,
+ * see below, or a batch so large that one launch over all its states would
+ * exceed a dispatch's 2^32 work-items), ENOMEM (workspace too small or
+ * allocation failed), EDEVICE.
+ * Tiling limit (M >= 2): the last two p axes, N_{M-1} x N_M points, are one
+ * LDS tile with N_M threads per row group; N_{M-1} needs a divisor d with
+ * d * N_M <= 256 and N_{M-1} <= 4 d.  Every size up to 16 qualifies, and so
+ * do equal pairs of 18, 20-22, 24, 27, 28 and 32; 17, 19, 23, 25, 26, 29-31
+ * and above 32 do not.  chfpe_workspace_bytes returns 0 for them. */
 int chfpe_setup(const chfpe_params *p, void *dev_workspace, size_t ws_bytes, void *hip_stream,
                 chfpe_ctx **out);
 
@@ -152,6 +160,18 @@ int chfpe_response_1d(chfpe_ctx *ctx, const chfpe_optical *A, int64_t n_t, int32
 int chfpe_response_2d(chfpe_ctx *ctx, const chfpe_optical *A, const chfpe_optical *B,
                       const chfpe_optical *C, int64_t n_t1, int64_t n_t2, int32_t stride1,
                       int32_t stride2, double dt, double *R);
+
+/* Columns j1_begin <= j1 < j1_end of the same R (t1 = j1 stride1 dt):
+ * R receives [n_t2][j1_end - j1_begin], t1 fastest.  U = A^x W_eq is first
+ * advanced to the first column's t1 (j1_begin stride1 RK4 steps, FP64), so
+ * the columns equal those of one chfpe_response_2d call over 0..j1_end
+ * (bitwise for the FP64 path).  Ranges are the unit a caller spreads over
+ * several calls (progress between them) or several devices (each its own
+ * context).  Errors as for chfpe_response_2d; EINVAL also for
+ * j1_begin < 0 or j1_end < j1_begin. */
+int chfpe_response_2d_range(chfpe_ctx *ctx, const chfpe_optical *A, const chfpe_optical *B,
+                            const chfpe_optical *C, int64_t j1_begin, int64_t j1_end, int64_t n_t2,
+                            int32_t stride1, int32_t stride2, double dt, double *R);
 
 /* Number of values in a state: |{n : |n| <= K}| * prod_s Nq_s * Np_s. */
 int64_t chfpe_state_count(const chfpe_ctx *ctx);

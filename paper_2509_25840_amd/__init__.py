@@ -83,6 +83,8 @@ def lib():
     L.chfpe_response_1d.restype = ctypes.c_int
     L.chfpe_response_2d.argtypes = [vp, O, O, O, i64, i64, i32, i32, ctypes.c_double, dp]
     L.chfpe_response_2d.restype = ctypes.c_int
+    L.chfpe_response_2d_range.argtypes = [vp, O, O, O, i64, i64, i64, i32, i32, ctypes.c_double, dp]
+    L.chfpe_response_2d_range.restype = ctypes.c_int
     L.chfpe_state_count.argtypes = [vp]
     L.chfpe_state_count.restype = i64
     L.chfpe_get_state.argtypes = [vp, dp]
@@ -385,6 +387,15 @@ class Solver:
         self._check(lib().chfpe_response_2d(self._ctx, ctypes.byref(oa), ctypes.byref(ob), ctypes.byref(oc),
                                             int(n_t1), int(n_t2), int(stride1), int(stride2), float(dt),
                                             _dptr(R)))
+        return R
+
+    def response_2d_range(self, A: dict, B: dict, C: dict, j1_begin: int, j1_end: int, n_t2: int,
+                          stride1: int, stride2: int, dt: float) -> np.ndarray:
+        R = np.empty((int(n_t2), int(j1_end) - int(j1_begin)))
+        oa, ob, oc = optical_from_dict(A), optical_from_dict(B), optical_from_dict(C)
+        self._check(lib().chfpe_response_2d_range(self._ctx, ctypes.byref(oa), ctypes.byref(ob), ctypes.byref(oc),
+                                                  int(j1_begin), int(j1_end), int(n_t2), int(stride1),
+                                                  int(stride2), float(dt), _dptr(R)))
         return R
 
     def get_state(self) -> np.ndarray:

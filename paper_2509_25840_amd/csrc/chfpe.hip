@@ -73,6 +73,46 @@ struct Derived {
   std::vector<int> nvec;  // ne * M
 };
 
+// A dispatch's grid size counts work-items in 32 bits: every launch must stay
+// within it (a larger one would wrap and leave tasks unrun).
+constexpr long long kMaxGridItems = 0xFFFFFFFFLL;
+
+// work-items of a launch of ntasks workgroups, padded to a multiple of 8
+long long grid_items(long long ntasks, int threads) { return (ntasks + 7) / 8 * 8 * (long long)threads; }
+
+// The k_pblock tile of the innermost p axes (one, or the last two): RG row
+// groups of cols threads, each thread covering up to kPBlockRPT rows of a
+// task's run of nb blocks.  RG divides rows (two or three modes), so a row
+// batch lies in one block.  nb_hi: most blocks per task the row coverage and
+// the LDS budget allow; nb_lo: fewest for which the launch over every state
+// of the largest batch fits one dispatch.
+struct PBShape {
+  int NB, rows, cols, RG, nblocks, nb_lo, nb_hi;
+  size_t blk_bytes;
+  long long items(const Derived &d, int nb) const {
+    const long long tasks = (long long)d.ne * (d.batched ? d.B : 1) * ((nblocks + nb - 1) / nb);
+    return grid_items(tasks, RG * cols);
+  }
+};
+
+PBShape pblock_shape(const Derived &d) {
+  PBShape s{};
+  const int M = d.M;
+  s.NB = M == 1 ? 1 : 2;
+  s.cols = d.Np[M - 1];
+  s.rows = M == 1 ? 1 : d.Np[M - 2];
+  s.RG = std::max(1, kPBlockThreads / s.cols);
+  if (s.NB == 2)
+    while (s.rows % s.RG) --s.RG;
+  s.nblocks = (int)(d.E / ((long long)s.rows * s.cols));
+  s.blk_bytes = (size_t)s.NB * s.rows * (s.cols + 1) * sizeof(double);
+  long long hi = std::min<long long>((long long)kPBlockRPT * s.RG / s.rows, (long long)(80 * 1024 / s.blk_bytes));
+  s.nb_hi = (int)std::max<long long>(1, std::min<long long>(hi, s.nblocks));
+  s.nb_lo = 1;
+  while (s.nb_lo < s.nb_hi && s.items(d, s.nb_lo) > kMaxGridItems) ++s.nb_lo;
+  return s;
+}
+
 bool derive(const chfpe_params *p, Derived &d, std::string &err) {
   if (!p) {
     err = "params is NULL";
@@ -160,6 +200,16 @@ bool derive(const chfpe_params *p, Derived &d, std::string &err) {
   d.S = d.E * d.ne;
   if (d.E >= (1LL << 29)) {  // byte offsets within an element fit 32 bits
     err = "one element must have fewer than 2^29 points";
+    return false;
+  }
+  const PBShape ps = pblock_shape(d);
+  if (ps.rows > kPBlockRPT * ps.RG) {
+    err = "the last two p axes (" + std::to_string(ps.rows) + " x " + std::to_string(ps.cols) +
+          " points) cannot be tiled: N_{M-1} needs a divisor d with d * N_M <= 256 and N_{M-1} <= 4 d";
+    return false;
+  }
+  if (ps.items(d, ps.nb_lo) > kMaxGridItems) {
+    err = "batch too large: the p-block launch over every branch state exceeds one dispatch (2^32 work-items)";
     return false;
   }
   return true;
@@ -486,7 +536,8 @@ QPass make_qpass(chfpe_ctx *c, int a, int b, int run, std::vector<int> rest, int
   q.nrest = q.rN[0] * q.rN[1] * q.rN[2];
   q.pc = std::min(pc, run);
   q.nchunk = (run + q.pc - 1) / q.pc;
-  q.ntasks = d.ne * q.nrest * q.nchunk;
+  // (saturates: plan() then finds the launch too large for one dispatch)
+  q.ntasks = (int)std::min<long long>((long long)d.ne * q.nrest * q.nchunk, 1LL << 30);
   q.nblk = pad8(q.ntasks);
   q.ca_a = axis_ca(g, a);
   q.cb_a = axis_cb(g, a);
@@ -516,31 +567,29 @@ void plan_one(chfpe_ctx *c, int a, int run, std::vector<int> rest, QPass &out, i
   nmax = nmax_bucket(axis_len(c->d, a));
 }
 
-// Choose tile shapes.
-void plan(chfpe_ctx *c) {
+// Choose tile shapes.  Returns false when a k_qpass launch over every state
+// of the largest batch would exceed one dispatch (the k_pblock shape always
+// fits: derive() checked it).
+bool plan(chfpe_ctx *c) {
   const Derived &d = c->d;
   Launch &ln = c->ln;
   const int M = d.M;
   const int NpM = d.Np[M - 1];
   // k_pblock: the innermost one (one mode) or two p axes
   PBlock &pb = ln.pb;
-  pb.NB = M == 1 ? 1 : 2;
-  pb.cols = NpM;
-  pb.rows = M == 1 ? 1 : d.Np[M - 2];
+  const PBShape ps = pblock_shape(d);  // derive() checked rows <= kPBlockRPT RG and nb_lo's grid
+  pb.NB = ps.NB;
+  pb.cols = ps.cols;
+  pb.rows = ps.rows;
   pb.B = pb.rows * pb.cols;
-  pb.nblocks = (int)(d.E / pb.B);
+  pb.nblocks = ps.nblocks;
   pb.bpq = d.P / pb.B;
-  pb.RG = std::max(1, kPBlockThreads / pb.cols);
-  if (pb.NB == 2)  // row groups divide the rows: the block of a row batch is uniform
-    while (pb.rows % pb.RG) --pb.RG;
-  // lines per task ~ threads; rows per thread <= kPBlockRPT; LDS <= ~80 KB
-  const size_t blk_bytes = (size_t)pb.NB * pb.rows * (NpM + 1) * sizeof(double);
+  pb.RG = ps.RG;  // row groups divide the rows: the block of a row batch is uniform
+  // lines per task ~ threads, within [nb_lo, nb_hi] (row coverage, LDS, grid)
   const int lines_per_blk = pb.rows + (pb.NB == 2 ? pb.cols : 0);
   int nb = std::max(1, (pb.RG * pb.cols) / lines_per_blk);
   if (c->tune_pb_nb > 0) nb = c->tune_pb_nb;
-  while (nb > 1 && ((long long)nb * pb.rows > (long long)kPBlockRPT * pb.RG || nb * blk_bytes > 80 * 1024))
-    --nb;
-  nb = std::min(nb, pb.nblocks);
+  nb = std::max(ps.nb_lo, std::min(nb, ps.nb_hi));
   pb.nb = nb;
   pb.split = c->tune_pb_split >= 0 ? (c->tune_pb_split != 0) : 1;
   ln.pb_nmax = nmax_bucket(std::max(pb.rows, pb.cols));
@@ -574,6 +623,10 @@ void plan(chfpe_ctx *c) {
     ln.has_qx = true;
     plan_one(c, M + 0, plane, {0, 1, 2}, ln.qx, ln.qx_threads, ln.qx_nmax);
   }
+  const long long nbat = d.batched ? d.B : 1;
+  auto fits = [&](const QPass &q, int thr) { return grid_items((long long)q.ntasks * nbat, thr) <= kMaxGridItems; };
+  return fits(ln.qf, ln.qf_threads) && (!ln.has_qa || fits(ln.qa, ln.qa_threads)) &&
+         (!ln.has_qx || fits(ln.qx, ln.qx_threads));
 }
 
 // --------------------------------------------------------------------------
@@ -1252,7 +1305,16 @@ int chfpe_setup(const chfpe_params *p, void *dev_workspace, size_t ws_bytes, voi
       return fail(nullptr, CHFPE_EINVAL, "box too large: exp(-beta H/2) underflows at its edge");
     }
   }
-  plan(c);
+  if (!plan(c)) {  // requested q tiles too small for this batch: automatic ones
+    c->tune_pb_nb = 0;
+    c->tune_pb_split = -1;
+    c->tune_q_pc = 0;
+    if (!plan(c)) {
+      chfpe_destroy(c);
+      return fail(nullptr, CHFPE_EINVAL,
+                  "batch too large: a q-pass launch over every branch state exceeds one dispatch (2^32 work-items)");
+    }
+  }
 
   auto up_copy = [&](void *dst, const void *src, size_t bytes) {
     return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream);
@@ -1395,14 +1457,16 @@ int chfpe_response_1d(chfpe_ctx *c, const chfpe_optical *A, int64_t n_t, int32_t
   return CHFPE_OK;
 }
 
-int chfpe_response_2d(chfpe_ctx *c, const chfpe_optical *A, const chfpe_optical *B, const chfpe_optical *C,
-                      int64_t n_t1, int64_t n_t2, int32_t stride1, int32_t stride2, double dt, double *R) {
+int chfpe_response_2d_range(chfpe_ctx *c, const chfpe_optical *A, const chfpe_optical *B,
+                            const chfpe_optical *C, int64_t j1_begin, int64_t j1_end, int64_t n_t2, int32_t stride1,
+                            int32_t stride2, double dt, double *R) {
   if (!c) return CHFPE_EINVAL;
-  if (!optical_ok(A, c->d.M) || !optical_ok(B, c->d.M) || !optical_ok(C, c->d.M) || n_t1 < 0 || n_t2 < 0 ||
-      stride1 < 0 || stride2 < 0 || (n_t1 > 1 && stride1 < 1) || (n_t2 > 1 && stride2 < 1) || !R ||
-      !std::isfinite(dt) || ((n_t1 > 1 || n_t2 > 1) && !(dt > 0)))
+  if (!optical_ok(A, c->d.M) || !optical_ok(B, c->d.M) || !optical_ok(C, c->d.M) || j1_begin < 0 ||
+      j1_end < j1_begin || n_t2 < 0 || stride1 < 0 || stride2 < 0 || (j1_end > 1 && stride1 < 1) ||
+      (n_t2 > 1 && stride2 < 1) || !R || !std::isfinite(dt) || ((j1_end > 1 || n_t2 > 1) && !(dt > 0)))
     return fail(c, CHFPE_EINVAL, "invalid response arguments");
   if (!c->has_eq) return fail(c, CHFPE_ESTATE, "no equilibrium: call chfpe_equilibrate first");
+  const int64_t n_t1 = j1_end - j1_begin;  // columns computed here
   const int64_t n = n_t1 * n_t2;
   if (n == 0) return CHFPE_OK;
   int rc = ensure_rbuf(c, (size_t)(n + (c->d.batched ? (int64_t)c->d.B * n_t2 : 0)));
@@ -1414,8 +1478,12 @@ int chfpe_response_2d(chfpe_ctx *c, const chfpe_optical *A, const chfpe_optical 
   HIPCHK(c, hipMemcpyAsync(c->gA, ga.data(), ga.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->gB, gb.data(), gb.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->Cw, ct.data(), ct.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
-  // U = A^x W_eq
+  // U = A^x W_eq, advanced to the first column's t1
   launch_perturb<double>(c, c->weq, c->u, c->gA);
+  if (j1_begin > 0) {
+    rc = rk4(c, c->u, j1_begin * stride1, dt);
+    if (rc) return rc;
+  }
   if (c->d.batched) {
     rc = c->d.prec == CHFPE_FP32 ? branches_batched<float>(c, n_t1, n_t2, stride1, stride2, dt)
                                  : branches_batched<double>(c, n_t1, n_t2, stride1, stride2, dt);
@@ -1443,6 +1511,13 @@ int chfpe_response_2d(chfpe_ctx *c, const chfpe_optical *A, const chfpe_optical 
   for (int64_t j = 0; j < n; ++j)
     if (!std::isfinite(R[j])) return fail(c, CHFPE_ENONFINITE, "response became non-finite");
   return CHFPE_OK;
+}
+
+int chfpe_response_2d(chfpe_ctx *c, const chfpe_optical *A, const chfpe_optical *B, const chfpe_optical *C,
+                      int64_t n_t1, int64_t n_t2, int32_t stride1, int32_t stride2, double dt, double *R) {
+  if (!c) return CHFPE_EINVAL;
+  if (n_t1 < 0) return fail(c, CHFPE_EINVAL, "invalid response arguments");
+  return chfpe_response_2d_range(c, A, B, C, 0, n_t1, n_t2, stride1, stride2, dt, R);
 }
 
 int64_t chfpe_state_count(const chfpe_ctx *c) { return c ? c->d.S : 0; }
@@ -1572,7 +1647,7 @@ int chfpe_autotune(chfpe_ctx *c, int32_t n_steps) {
     c->tune_pb_nb = best.pb_nb;
     c->tune_pb_split = best.pb_split;
     c->tune_q_pc = best.q_pc;
-    plan(c);
+    (void)plan(c);  // the starting shape, or one that fit when timed
     c->timing_every = timing;
     return rc;
   };
@@ -1580,7 +1655,7 @@ int chfpe_autotune(chfpe_ctx *c, int32_t n_steps) {
     c->tune_pb_nb = t.pb_nb;
     c->tune_pb_split = t.pb_split;
     c->tune_q_pc = t.q_pc;
-    plan(c);
+    if (!plan(c)) return CHFPE_OK;  // too large a launch for one dispatch: not a candidate
     const std::vector<int> eff = {c->ln.pb.nb, c->ln.pb.split, c->ln.qf.pc, c->ln.qa.pc};
     for (const auto &s : seen)
       if (s == eff) return CHFPE_OK;  // same launches as a shape already timed

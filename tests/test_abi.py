@@ -97,3 +97,35 @@ def test_null_context_calls_are_rejected(binding):
     buf = (ctypes.c_int32 * 6)()
     assert L.chfpe_tile_config(None, buf, 6) == binding.CHFPE_EINVAL
     L.chfpe_destroy(None)
+
+
+def test_p_block_tiling_limit_is_enforced(binding):
+    # the last two p axes are one LDS tile: N_{M-1} needs a divisor d with
+    # d * N_M <= 256 and N_{M-1} <= 4 d, otherwise rows would go uncovered
+    w = wl.workload("two_mode_32")
+    for n, ok in ((16, True), (17, False), (24, True), (25, False), (32, True), (33, False), (48, False)):
+        p = binding.params_from_workload(w)
+        p.Np[0], p.Np[1] = n, n
+        assert (binding.workspace_bytes(p) > 0) == ok, n
+    p = binding.params_from_workload(w)
+    p.Np[0], p.Np[1] = 17, 8        # 17 rows: divisor 17 with 17 * 8 <= 256
+    assert binding.workspace_bytes(p) > 0
+    p.Np[0], p.Np[1] = 8, 48        # one row group of 8 rows x 48 columns
+    assert binding.workspace_bytes(p) > 0
+    one = binding.params_from_workload(wl.workload("one_mode_48"))
+    assert binding.workspace_bytes(one) > 0    # one mode: rows of one p axis only
+
+
+def test_batch_beyond_one_dispatch_is_rejected(binding):
+    # 10 elements of 16^6 points: a p-block launch over 64 states needs at
+    # least 3 blocks per task to stay within 2^32 work-items, and none of the
+    # allowed shapes (at most 4) fits 1024 states
+    w = wl.workload("three_mode_16")
+    p = binding.params_from_workload(w, batch=64)
+    assert binding.workspace_bytes(p) > 0
+    p = binding.params_from_workload(w, batch=1024)
+    assert binding.workspace_bytes(p) == 0
+    L = binding.lib()
+    ctx = ctypes.c_void_p()
+    assert L.chfpe_setup(ctypes.byref(p), None, 0, None, ctypes.byref(ctx)) == binding.CHFPE_EINVAL
+    assert b"dispatch" in L.chfpe_last_error(None)

@@ -326,3 +326,76 @@ def test_autotune_keeps_state_and_results(pk):
     assert rel_l2(got, ref) < FP64_TOL
     with pk.Solver(p) as s2:
         assert s2.tile_config() == cfg
+
+
+@pytest.mark.parametrize("batch", [1, 3])
+def test_response_2d_range_equals_the_full_columns(pk, batch):
+    """Column ranges of R (chfpe_response_2d_range) reproduce the columns of
+    one full call bitwise, single-state and in batched waves."""
+    w = SMALL["m2_n12_k3"]
+    A, B = _ops(2)
+    say(f"[range] batch {batch}")
+    with pk.Solver(pk.params_from_workload(w, precision=pk.CHFPE_FP64, batch=batch)) as s:
+        s.equilibrate(5, 0.004)
+        full = s.response_2d(A, B, A, 7, 4, 2, 2, 0.004)
+        parts = [s.response_2d_range(A, B, A, j0, j1, 4, 2, 2, 0.004) for j0, j1 in ((0, 3), (3, 4), (4, 7))]
+    assert np.array_equal(full, np.concatenate(parts, axis=1))
+
+
+TILE_CANDIDATES = [
+    {"CHFPE_TUNE_PB_NB": "1"}, {"CHFPE_TUNE_PB_NB": "2"}, {"CHFPE_TUNE_PB_NB": "8"},
+    {"CHFPE_TUNE_PB_SPLIT": "0"},
+    {"CHFPE_TUNE_Q_PC": "4"}, {"CHFPE_TUNE_Q_PC": "8"}, {"CHFPE_TUNE_Q_PC": "32"},
+]
+
+
+@pytest.mark.parametrize("name", ["m2_n12_k3", "m3_p8_k2", "m3_n8_k2", "m3_n16_k2"])
+def test_every_autotuner_tile_shape_matches_the_oracle(pk, monkeypatch, name):
+    """Each tile shape chfpe_autotune may pick gives the oracle's RK4 steps."""
+    w = SMALL[name] if name in SMALL else wl.workload("three_mode_24", Nq=[5, 6, 16], Np=[6, 16, 16], K=2)
+    W = phys_state(w, seed=21)
+    ref = orc.rk4(w, W, 2, 0.002)
+    bad = []
+    for env in TILE_CANDIDATES:
+        for k in ("CHFPE_TUNE_PB_NB", "CHFPE_TUNE_PB_SPLIT", "CHFPE_TUNE_Q_PC"):
+            monkeypatch.delenv(k, raising=False)
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        with solver(pk, w) as s:
+            s.set_state(W)
+            s.propagate(2, 0.002)
+            err = rel_l2(s.get_state().reshape(W.shape), ref)
+            cfg = s.tile_config()
+        say(f"[tiles] {name} {env} -> {cfg} err {err:.2e}")
+        if not err < 1e-13:
+            bad.append((env, cfg, err))
+    assert not bad, bad
+
+
+def test_batched_launch_stays_within_one_dispatch(pk, monkeypatch):
+    """Ten elements of 16^6 points in a wave of 32 FP32 branch states: at one
+    p-block per task that launch would pass 2^32 work-items (a dispatch's
+    limit), so the planner raises the request to two blocks per task.  The
+    32 columns then match the single-state FP64 solver (which keeps one)."""
+    import torch
+    monkeypatch.setenv("CHFPE_TUNE_PB_NB", "1")
+    w = wl.workload("three_mode_16")
+    dt = w["dt"]
+    A, B, C = w["A"], w["B"], w["C"]
+    n_eq, nc, n2 = 50, 32, 3
+    say("[dispatch] three_mode_16 single FP64")
+    with pk.Solver(pk.params_from_workload(w, precision=pk.CHFPE_FP64, batch=1)) as s:
+        assert s.tile_config()["pblock_blocks_per_task"] == 1
+        s.equilibrate(n_eq, dt)
+        R1 = s.response_2d_range(A, B, C, 0, nc, n2, 1, 1, dt)
+    torch.cuda.empty_cache()
+    say("[dispatch] three_mode_16 batch 32 FP32")
+    with pk.Solver(pk.params_from_workload(w, precision=pk.CHFPE_FP32, batch=32)) as sb:
+        cfg = sb.tile_config()
+        assert cfg["pblock_blocks_per_task"] == 2, cfg
+        sb.equilibrate(n_eq, dt)
+        RB = sb.response_2d_range(A, B, C, 0, nc, n2, 1, 1, dt)
+    torch.cuda.empty_cache()
+    err = float(np.abs(RB - R1).max() / np.abs(R1).max())
+    say(f"[dispatch] max rel diff {err:.3e}")
+    assert err < 1e-4
