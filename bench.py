@@ -309,6 +309,11 @@ def main(argv=None):
                     help="closure: EQ,N_T1,N_T2,STRIDE of the judged responses (default: the workload's)")
     ap.add_argument("--ref-batch", type=int, default=0,
                     help="precision: branch batch of the FP64 reference run (0: --batch)")
+    ap.add_argument("--legs", default="f64,f32",
+                    help="precision: the runs made here (f64, f32 or both); results of the others "
+                         "come from --leg-dir")
+    ap.add_argument("--leg-dir", default="",
+                    help="precision: folder each leg's R, spectrum and timing are saved to and read from")
     ap.add_argument("--trace-dir", help="summarise: rocprofv3 --kernel-trace --stats output folder")
     ap.add_argument("--fetch-dir", help="summarise: rocprofv3 --pmc FETCH_SIZE output folder")
     ap.add_argument("--write-dir", help="summarise: rocprofv3 --pmc WRITE_SIZE output folder")
@@ -454,8 +459,19 @@ def main(argv=None):
         solver.close()
         out = {"mode": "precision", "workload": args.workload}
         res = {}
+        legs = [x for x in args.legs.split(",") if x]
         for prec_name, pcode, nb in (("f64", pk.CHFPE_FP64, args.ref_batch or args.batch),
                                      ("f32", pk.CHFPE_FP32, args.batch)):
+            leg_file = os.path.join(args.leg_dir, f"precision_{args.workload}_{prec_name}.npz") if args.leg_dir else ""
+            if prec_name not in legs:
+                if not leg_file or not os.path.exists(leg_file):
+                    log(f"[precision] {prec_name}: not run here and no saved leg")
+                    continue
+                z = np.load(leg_file)
+                res[prec_name] = (z["R"], z["I"])
+                out[prec_name] = json.loads(str(z["meta"]))
+                log(f"[precision] {prec_name}: read {leg_file}")
+                continue
             s = pk.Solver(pk.params_from_workload(w, precision=pcode, batch=nb))
             tiles = s.tile_config() if args.no_autotune else s.autotune(1)
             torch.cuda.synchronize()
@@ -478,7 +494,13 @@ def main(argv=None):
             s.close()
             res[prec_name] = (R, I)
             out[prec_name] = {"seconds": el, "updates_per_s": S * steps_per / el, "batch": nb, "tiles": tiles}
+            if leg_file:
+                os.makedirs(args.leg_dir, exist_ok=True)
+                np.savez(leg_file, R=R, I=I, meta=json.dumps(out[prec_name]))
             log(f"[precision] {prec_name}: {el:.2f} s")
+        if "f64" not in res or "f32" not in res:
+            print(json.dumps(out), flush=True)
+            return 0
         (R64, I64), (R32, I32) = res["f64"], res["f32"]
         out["speedup_f32_over_f64"] = out["f64"]["seconds"] / out["f32"]["seconds"]
         out["R_rel_l2"] = float(np.linalg.norm(R32 - R64) / np.linalg.norm(R64))
