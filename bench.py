@@ -105,7 +105,7 @@ def _kind_of(short: str, grid: int, min_grid: dict):
     fam = short.split("<")[0]
     targs = [a.strip() for a in short[short.find("<") + 1:short.rfind(">")].split(",")] if "<" in short else []
     if fam == "k_pblock":
-        kind = "perturb" if targs[-1] == "true" else "pblock_rhs"
+        kind = "perturb" if targs[5] == "true" else "pblock_rhs"  # <T, TO, NMAX, RPT, MM, PERTURB, CLOS>
     elif fam == "k_qpass":
         if int(targs[5]) == 2:        # dX/dq field: second launch of a perturbation
             kind = "perturb_q"
