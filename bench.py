@@ -307,6 +307,12 @@ def main(argv=None):
                     help="closure: fine-run equilibration steps, steps after each excitation, snapshot spacing")
     ap.add_argument("--judge", default="",
                     help="closure: EQ,N_T1,N_T2,STRIDE of the judged responses (default: the workload's)")
+    ap.add_argument("--closure-stage", choices=["all", "moments", "fine", "final"], default="all",
+                    help="closure: all in one run, or in stages that save to and read from --leg-dir: "
+                         "moments (draws of --closure-draw-range), fine (judge columns --judge-cols of "
+                         "the fine FP64 response), final (train, coarse runs, comparison)")
+    ap.add_argument("--closure-draw-range", default="", help="closure moments stage: FIRST:END draw seeds")
+    ap.add_argument("--judge-cols", default="", help="closure fine stage: FIRST:END t1 columns")
     ap.add_argument("--ref-batch", type=int, default=0,
                     help="precision: branch batch of the FP64 reference run (0: --batch)")
     ap.add_argument("--legs", default="f64,f32",
@@ -400,22 +406,75 @@ def main(argv=None):
         wc["Nq"] = [n // 2 for n in w["Nq"]]
         wc["Np"] = [n // 2 for n in w["Np"]]
         n_eq, n_prop, every = (int(x) for x in args.closure_snap.split(","))
+        stage = args.closure_stage
+        if stage != "all" and not args.leg_dir:
+            log("[closure] staged runs need --leg-dir")
+            return 2
+        mom_file = lambda sd: os.path.join(args.leg_dir, f"closure_moments_{args.workload}_{sd}.npz")
+        if args.judge:
+            j_eq, j1, j2, js = (int(x) for x in args.judge.split(","))
+        else:
+            j_eq, j1, j2, js = int(w["eq_steps"]), int(w["n_t1"]), int(w["n_t2"]), int(w["stride1"])
+        judged = [("nominal", wc)] + [(f"held_{1000 + k}", wl.draw_perturbed(wc, 1000 + k))
+                                      for k in range(args.closure_held)]
+        mem = torch.cuda.get_device_properties(0).total_memory
+
+        if stage == "moments":
+            a, b = (int(x) for x in args.closure_draw_range.split(":"))
+            os.makedirs(args.leg_dir, exist_ok=True)
+            t0 = time.perf_counter()
+            for sd in range(a, b):
+                mom = clo.fine_moments(wl.draw_perturbed(wc, sd), n_eq, n_prop, every, dt,
+                                       progress=lambda n: log(f"[closure] draw {sd}: snapshot {n} "
+                                                              f"({time.perf_counter() - t0:.1f} s)"))
+                clo.save_moments(mom_file(sd), mom)
+                log(f"[closure] moments of draw {sd} saved ({time.perf_counter() - t0:.1f} s)")
+            print(json.dumps({"mode": "closure", "stage": "moments", "fine_workload": args.workload,
+                              "draws": [a, b], "snapshots": args.closure_snap,
+                              "seconds": time.perf_counter() - t0}), flush=True)
+            return 0
+
+        def fine_file(name, c0, c1):
+            return os.path.join(args.leg_dir, f"closure_fine_{args.workload}_{name}_{j_eq}_{j2}_{js}_{c0}_{c1}.npz")
+
+        if stage == "fine":
+            c0, c1 = (int(x) for x in args.judge_cols.split(":")) if args.judge_cols else (0, j1)
+            os.makedirs(args.leg_dir, exist_ok=True)
+            for name, wj in judged:
+                wf = clo.fine_of(wj)
+                t0 = time.perf_counter()
+                with pk.Solver(pk.params_from_workload(wf, precision=pk.CHFPE_FP64, batch=1)) as s:
+                    s.equilibrate(j_eq, dt)
+                    torch.cuda.synchronize()
+                    t_eq = time.perf_counter() - t0
+                    log(f"[closure] fine {name}: equilibrated ({t_eq:.1f} s)")
+                    cols = []
+                    for c in range(c0, c1):  # one column per call: progress between calls
+                        cols.append(s.response_2d_range(wf["A"], wf["B"], wf["C"], c, c + 1, j2, js, js, dt))
+                        log(f"[closure] fine {name}: column {c} ({time.perf_counter() - t0:.1f} s)")
+                    torch.cuda.synchronize()
+                # column time includes re-advancing U to each column's t1 (an upper bound)
+                np.savez(fine_file(name, c0, c1), R=np.concatenate(cols, axis=1), eq_seconds=t_eq,
+                         col_seconds=time.perf_counter() - t0 - t_eq)
+            print(json.dumps({"mode": "closure", "stage": "fine", "fine_workload": args.workload,
+                              "judge": [j_eq, j1, j2, js], "cols": [c0, c1]}), flush=True)
+            return 0
+
         t0 = time.perf_counter()
         draws = []
         for sd in range(args.closure_draws):
             wd = wl.draw_perturbed(wc, sd)
-            draws.append((wd, clo.fine_moments(wd, n_eq, n_prop, every, dt)))
-            log(f"[closure] moments of draw {sd}")
+            if stage == "final":
+                draws.append((wd, clo.load_moments(mom_file(sd))))
+            else:
+                draws.append((wd, clo.fine_moments(wd, n_eq, n_prop, every, dt)))
+                log(f"[closure] moments of draw {sd}")
         data = clo.training_set(draws)
         t_data = time.perf_counter() - t0
         t0 = time.perf_counter()
         tr, hist = clo.train(data, args.closure_steps, args.closure_lr)
         t_train = time.perf_counter() - t0
         log(f"[closure] trained: loss {hist[0]:.4e} -> {hist[-1]:.4e} ({t_train:.2f} s)")
-        if args.judge:
-            j_eq, j1, j2, js = (int(x) for x in args.judge.split(","))
-        else:
-            j_eq, j1, j2, js = int(w["eq_steps"]), int(w["n_t1"]), int(w["n_t2"]), int(w["stride1"])
 
         def spectrum(wk, nb, sv=None):
             with pk.Solver(pk.params_from_workload(wk, precision=pk.CHFPE_FP64, batch=nb)) as s:
@@ -429,14 +488,30 @@ def main(argv=None):
                 torch.cuda.synchronize()
                 return R, I, time.perf_counter() - ts
 
-        judged = [("nominal", wc)] + [(f"held_{1000 + k}", wl.draw_perturbed(wc, 1000 + k))
-                                      for k in range(args.closure_held)]
+        def saved_fine(name):
+            # the fine columns of earlier fine-stage runs, in order, covering 0..j1
+            parts, c, secs = [], 0, None
+            while c < j1:
+                hits = [f for f in os.listdir(args.leg_dir)
+                        if f.startswith(f"closure_fine_{args.workload}_{name}_{j_eq}_{j2}_{js}_{c}_")]
+                if not hits:
+                    raise SystemExit(f"closure final: no saved fine columns from {c} for {name}")
+                c1 = max(int(f[:-4].rsplit("_", 1)[1]) for f in hits)
+                z = np.load(fine_file(name, c, c1))
+                parts.append(z["R"])
+                secs = (float(z["eq_seconds"]) if secs is None else secs) + float(z["col_seconds"])
+                c = c1
+            R = np.concatenate(parts, axis=1)[:, :j1]
+            return R, pk.spectrum_2d(R, js * dt, js * dt), secs
+
         rows = []
         for name, wj in judged:
             wf = clo.fine_of(wj)
-            nbf = auto_batch(pk, {**wf, "n_t1": j1}, pk.CHFPE_FP64, torch.cuda.get_device_properties(0).total_memory)
-            nbc = auto_batch(pk, {**wj, "n_t1": j1}, pk.CHFPE_FP64, torch.cuda.get_device_properties(0).total_memory)
-            Rf, If, tf = spectrum(wf, nbf)
+            nbc = auto_batch(pk, {**wj, "n_t1": j1}, pk.CHFPE_FP64, mem)
+            if stage == "final":
+                Rf, If, tf = saved_fine(name)
+            else:
+                Rf, If, tf = spectrum(wf, auto_batch(pk, {**wf, "n_t1": j1}, pk.CHFPE_FP64, mem))
             Rp, Ip, tp = spectrum(wj, nbc)
             Rc, Ic, tc = spectrum(wj, nbc, clo.entries(tr.prm, wj))
             e = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
@@ -445,7 +520,7 @@ def main(argv=None):
                          "R_err_plain": e(Rp, Rf), "R_err_closure": e(Rc, Rf)})
             log(f"[closure] {name}: plain {rows[-1]['spectrum_err_plain']:.3e} "
                 f"closure {rows[-1]['spectrum_err_closure']:.3e} fine {tf:.2f} s coarse {tc:.2f} s")
-        out = {"mode": "closure", "fine_workload": args.workload, "coarse_grid": wc["Nq"] + wc["Np"],
+        out = {"mode": "closure", "stage": stage, "fine_workload": args.workload, "coarse_grid": wc["Nq"] + wc["Np"],
                "draws": args.closure_draws, "snapshots": args.closure_snap, "steps": args.closure_steps,
                "lr": args.closure_lr, "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
                "data_s": t_data, "train_s": t_train, "judge": [j_eq, j1, j2, js], "cases": rows,

@@ -20,23 +20,28 @@ def fine_of(w: dict) -> dict:
     return f
 
 
-def fine_moments(w: dict, n_eq: int, n_prop: int, every: int, dt: float):
+def fine_moments(w: dict, n_eq: int, n_prop: int, every: int, dt: float, progress=None):
     """Moments of fine-grid snapshots along the states a 2D response visits:
     W_eq after n_eq steps, then A^x W_eq and B^x of it, each propagated
     n_prop steps with a snapshot every `every` steps.  Returns per axis
-    (G_a, b_a) and the (c_a, t_a) array, summed over the snapshots."""
+    (G_a, b_a) and the (c_a, t_a) array, summed over the snapshots.
+    `progress(n)`, if given, is called after each snapshot n."""
     wf = fine_of(w)
     acc = None
+    n_snap = 0
     with Solver(params_from_workload(wf, precision=0, batch=1)) as s:
         s.equilibrate(n_eq, dt)
 
         def add():
-            nonlocal acc
+            nonlocal acc, n_snap
             G, b, ct = s.closure_moments()
             if acc is None:
                 acc = [G, b, ct]
             else:
                 acc = [[x + y for x, y in zip(acc[0], G)], [x + y for x, y in zip(acc[1], b)], acc[2] + ct]
+            n_snap += 1
+            if progress is not None:
+                progress(n_snap)
 
         add()
         for op in ("A", "B"):
@@ -46,6 +51,21 @@ def fine_moments(w: dict, n_eq: int, n_prop: int, every: int, dt: float):
                 s.propagate(every, dt)
                 add()
     return acc
+
+
+def save_moments(path: str, mom) -> None:
+    """Write one draw's moments (per axis G_a, b_a; the (c, t) array) to .npz."""
+    G, b, ct = mom
+    arrs = {f"G{a}": np.asarray(G[a]) for a in range(len(G))}
+    arrs.update({f"b{a}": np.asarray(b[a]) for a in range(len(b))})
+    np.savez(path, ct=np.asarray(ct), **arrs)
+
+
+def load_moments(path: str):
+    """Read moments written by save_moments."""
+    z = np.load(path)
+    n = len(z["ct"])
+    return [z[f"G{a}"] for a in range(n)], [z[f"b{a}"] for a in range(n)], z["ct"]
 
 
 def training_set(draws):
