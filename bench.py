@@ -313,6 +313,8 @@ def main(argv=None):
                          "the fine FP64 response), final (train, coarse runs, comparison)")
     ap.add_argument("--closure-draw-range", default="", help="closure moments stage: FIRST:END draw seeds")
     ap.add_argument("--judge-cols", default="", help="closure fine stage: FIRST:END t1 columns")
+    ap.add_argument("--judge-cases", default="",
+                    help="closure fine stage: comma-separated cases to run (nominal, held_1000, ...; default all)")
     ap.add_argument("--ref-batch", type=int, default=0,
                     help="precision: branch batch of the FP64 reference run (0: --batch)")
     ap.add_argument("--legs", default="f64,f32",
@@ -440,7 +442,10 @@ def main(argv=None):
         if stage == "fine":
             c0, c1 = (int(x) for x in args.judge_cols.split(":")) if args.judge_cols else (0, j1)
             os.makedirs(args.leg_dir, exist_ok=True)
+            only = [x for x in args.judge_cases.split(",") if x]
             for name, wj in judged:
+                if only and name not in only:
+                    continue
                 wf = clo.fine_of(wj)
                 t0 = time.perf_counter()
                 with pk.Solver(pk.params_from_workload(wf, precision=pk.CHFPE_FP64, batch=1)) as s:
