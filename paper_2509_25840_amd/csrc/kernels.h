@@ -197,6 +197,9 @@ __device__ __forceinline__ void compact_split(T *G, const int base, const int st
                                               T ca, T cb, const double *ct = nullptr) {
   static_assert(N % 2 == 0 && N >= 6, "split solve needs an even line of at least 6");
   constexpr int H = N / 2;
+  constexpr int R = CLOS ? 3 : 2;  // stencil reach
+  constexpr int NL = H + R;        // values this lane reads: its half and R past the middle
+  constexpr int PF = 2;            // LDS reads issued this many positions ahead of use
   constexpr double cm = kThomas.cp[H - 1];
   constexpr double inv1mc2 = 1.0 / (1.0 - cm * cm);
   const int step = half ? -stride : stride;
@@ -206,29 +209,41 @@ __device__ __forceinline__ void compact_split(T *G, const int base, const int st
     cb = -cb;
   }
   const double *cto = CLOS ? ct + (half ? kClosRows * kTab : 0) : ct;
-  constexpr int NL = CLOS ? H + 3 : H + 2;  // values this lane reads
+  // Streamed through LDS so that few values are live at once: the forward
+  // sweep stores d_i over f_i (already read), the back substitution stores
+  // x_i over d_i.  The partner lane (same wave) overwrites its half from its
+  // own end inward, so the R values past the middle are read before any
+  // store; own values are read PF + R positions ahead of the sweep.  f and
+  // dv are indexed by compile-time constants only (registers, not memory).
   T f[NL];
 #pragma unroll
-  for (int i = 0; i < NL; ++i) f[i] = G[start + i * step];
-  T d[H];
+  for (int j = H; j < NL; ++j) f[j] = G[start + j * step];
+#pragma unroll
+  for (int j = 0; j < H && j < R + PF; ++j) f[j] = G[start + j * step];
+  T dprev = T(0);
 #pragma unroll
   for (int i = 0; i < H; ++i) {
+    if (i + R + PF < H) f[i + R + PF < H ? i + R + PF : 0] = G[start + (i + R + PF) * step];
     const T fm1 = i >= 1 ? f[i >= 1 ? i - 1 : 0] : T(0);
     const T fm2 = i >= 2 ? f[i >= 2 ? i - 2 : 0] : T(0);
     const T fm3 = (CLOS && i >= 3) ? f[i >= 3 ? i - 3 : 0] : T(0);
     const T fp3 = CLOS ? f[i + 3 < NL ? i + 3 : NL - 1] : T(0);
     const T r = stencil_rhs<T, CLOS>(i, fm3, fm2, fm1, f[i + 1], f[i + 2], fp3, ca, cb, cto);
-    if (i == 0)
-      d[0] = r;
-    else  // d_i = (r_i - d_{i-1}/3) / pivot_i, one dependent FMA
-      d[i] = __builtin_fma(T(-kThomas.inv[i] / 3.0), d[i >= 1 ? i - 1 : 0], r * T(kThomas.inv[i]));
+    // d_i = (r_i - d_{i-1}/3) / pivot_i, one dependent FMA
+    const T d = i == 0 ? r : __builtin_fma(T(-kThomas.inv[i] / 3.0), dprev, r * T(kThomas.inv[i]));
+    G[start + i * step] = d;
+    dprev = d;
   }
-  const T other = __shfl_xor(d[H - 1], 1);
-  T x = (d[H - 1] - T(cm) * other) * T(inv1mc2);
+  const T other = __shfl_xor(dprev, 1);
+  T x = (dprev - T(cm) * other) * T(inv1mc2);
   G[start + (H - 1) * step] = x;
+  T dv[H];
+#pragma unroll
+  for (int j = H - 2; j >= 0 && j >= H - 2 - PF; --j) dv[j] = G[start + j * step];
 #pragma unroll
   for (int i = H - 2; i >= 0; --i) {
-    x = d[i] - T(kThomas.cp[i]) * x;
+    if (i - PF - 1 >= 0 && i - PF - 1 < H - 2 - PF) dv[i - PF - 1 >= 0 ? i - PF - 1 : 0] = G[start + (i - PF - 1) * step];
+    x = dv[i] - T(kThomas.cp[i]) * x;
     G[start + i * step] = x;
   }
 }
@@ -353,7 +368,7 @@ struct QPass {
 // T: type of X and of the arithmetic; TO: type of out.  A batch of nbatch
 // states is laid out [branch][n][q][p]; tasks cover every (branch, n).
 template <typename T, typename TO, int NMAX, int RPT, int MM, bool PERTURB, bool CLOS = false>
-__global__ void __launch_bounds__(256, (NMAX <= 24 || (NMAX == 32 && MM == 2)) ? 5 : NMAX <= 32 ? 4 : 3)
+__global__ void __launch_bounds__(256, (NMAX == 32 && MM == 2) ? 6 : NMAX <= 24 ? 5 : NMAX <= 32 ? 4 : 3)
 k_pblock(const Geom g, const Tabs tb, const PBlock pb, const T *__restrict__ X, TO *__restrict__ out,
          const double *__restrict__ grad) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
