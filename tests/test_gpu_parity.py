@@ -3,8 +3,10 @@
 Bar (FP64 path): relative L2 error <= 1e-10 on states, responses and
 observables; one right-hand side and a few RK4 steps agree to ~1e-14.
 Sizes: small grids that span several tiles with ragged tails, the one-mode
-workload at full size, and the two-mode 32^4 workload at full size in the
-launch configuration the benchmark times (sampled t1/t2 entries).
+workload at full size, the two-mode 32^4 workload at full size in the
+launch configuration the benchmark times (sampled t1/t2 entries), and the
+three-mode workloads at full size (12^6 and 16^6 whole states, 24^6 at
+sampled points of one right-hand side).
 """
 import sys
 
@@ -399,3 +401,70 @@ def test_batched_launch_stays_within_one_dispatch(pk, monkeypatch):
     err = float(np.abs(RB - R1).max() / np.abs(R1).max())
     say(f"[dispatch] max rel diff {err:.3e}")
     assert err < 1e-4
+
+
+@pytest.mark.parametrize("name,steps", [("three_mode_12", 2), ("three_mode_16", 1)])
+def test_three_mode_full_size_rhs_and_steps(pk, name, steps):
+    """Three modes at full size (12^6 and 16^6 grids, depth 2, 10 elements):
+    one right-hand side and RK4 steps on a seeded state, every value against
+    the oracle."""
+    import torch
+    w = wl.workload(name)
+    say(f"[full] {name}: rhs + {steps} RK4 steps")
+    W = phys_state(w, seed=7, noise=0.0)
+    ref_rhs = orc.rhs(w, W)
+    say(f"    oracle rhs done; {steps} oracle RK4 steps")
+    ref = orc.rk4(w, W, steps, w["dt"])
+    say("    oracle done; GPU")
+    with solver(pk, w) as s:
+        s.set_state(W)
+        s.rhs()
+        e_rhs = rel_l2(s.get_state(), ref_rhs)
+        s.set_state(W)
+        s.propagate(steps, w["dt"])
+        e_rk4 = rel_l2(s.get_state(), ref)
+    torch.cuda.empty_cache()
+    say(f"    rhs {e_rhs:.2e}  rk4 {e_rk4:.2e}")
+    assert e_rhs < 1e-13 and e_rk4 < 1e-13
+
+
+def test_three_mode_24_full_size_rhs_sampled(pk):
+    """Three modes on the full 24^6 grid (10 elements, 1.9e9 values): one
+    right-hand side on the GPU, checked at 96 seeded points and at the first
+    and last point of every element against the oracle's evaluation of the
+    same point (which reads only the lines through it)."""
+    import torch
+    w = wl.workload("three_mode_24")
+    say("[full] three_mode_24: building the state")
+    # element e: Boltzmann envelope of element 0 (a depth-0 call gives one
+    # element) times 1 + 0.3 x a seeded smooth field, built one element at a
+    # time to keep host memory near one state
+    w0 = {**w, "K": 0}
+    env = orc.boltzmann(w0)[0]
+    ne = orc.state_shape(w)[0]
+    W = np.empty(orc.state_shape(w))
+    for e in range(ne):
+        sm = wl.smooth_state(w0, seed=9 + e)[0]
+        sm *= 0.3 / np.abs(sm).max()
+        sm += 1.0
+        np.multiply(env, sm, out=W[e])
+        say(f"    element {e} built")
+    del env, sm
+    E = W[0].size
+    rng = np.random.default_rng(10)
+    pts = [(int(rng.integers(ne)), int(rng.integers(E))) for _ in range(96)]
+    pts += [(e, 0) for e in range(ne)] + [(e, E - 1) for e in range(ne)]
+    say("[full] three_mode_24: oracle points")
+    ref = np.array([orc.rhs_point(w, W, e, i) for e, i in pts])
+    with solver(pk, w) as s:
+        s.set_state(W)
+        say("[full] three_mode_24: rhs on the GPU")
+        s.rhs()
+        del W
+        got = s.get_state().reshape(ne, E)
+    torch.cuda.empty_cache()
+    g = np.array([got[e, i] for e, i in pts])
+    del got
+    err = float(np.abs(g - ref).max() / np.abs(ref).max())
+    say(f"    max error / max |rhs| over {len(pts)} points: {err:.2e}")
+    assert err < 1e-13
