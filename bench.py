@@ -291,8 +291,9 @@ def main(argv=None):
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the planner's default tile shapes (no chfpe_autotune before warmup)")
     ap.add_argument("--tiles", default="",
-                    help="NB,SPLIT,PC: fixed tile shapes (k_pblock blocks per task, lane-pair "
-                         "line solves 0/1, q-pass run positions per tile) instead of autotuning")
+                    help="NB,SPLIT,PC[,RUN]: fixed tile shapes (k_pblock blocks per task, lane-pair "
+                         "line solves 0/1, q-pass run positions per tile, k_pblock block groups "
+                         "per state in task order) instead of autotuning")
     ap.add_argument("--mode", choices=["bench", "kernels", "rk4", "summarise", "precision", "closure"],
                     default="bench",
                     help="kernels: a few RK4 steps of the workload (single state, then one "
@@ -338,10 +339,12 @@ def main(argv=None):
         return 2
 
     if args.tiles:
-        nb, split, pc = (int(x) for x in args.tiles.split(","))
+        vals = [int(x) for x in args.tiles.split(",")]
+        nb, split, pc = vals[:3]
         os.environ["CHFPE_TUNE_PB_NB"] = str(nb)
         os.environ["CHFPE_TUNE_PB_SPLIT"] = str(split)
         os.environ["CHFPE_TUNE_Q_PC"] = str(pc)
+        os.environ["CHFPE_TUNE_PB_RUN"] = str(vals[3] if len(vals) > 3 else 0)
         args.no_autotune = True
 
     import numpy as np
@@ -660,8 +663,8 @@ def main(argv=None):
     updates = float(S) * steps_per * args.steps
     value = updates / total
 
-    tiles_arg = "{},{},{}".format(tiles["request_pblock_blocks"], tiles["request_split"],
-                                  tiles["request_qpass_positions"])
+    tiles_arg = "{},{},{},{}".format(tiles["request_pblock_blocks"], tiles["request_split"],
+                                     tiles["request_qpass_positions"], tiles["request_pblock_run"])
     # roofline of the dominant kernel (largest share of the timed launches' time)
     share = {k: kt[k][0] * kt[k][1] for k in kt if kt[k][0] > 0}
     roofline = None

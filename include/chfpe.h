@@ -250,7 +250,10 @@ int chfpe_autotune(chfpe_ctx *ctx, int32_t n_steps);
  * stage-final q-pass; out[6..8] the requests these came from (blocks per
  * task, lane pairs, run positions; 0, -1, 0 = planner default), which the
  * CHFPE_TUNE_PB_NB, CHFPE_TUNE_PB_SPLIT and CHFPE_TUNE_Q_PC environment
- * variables reproduce.  Writes min(n, 9) values and returns that count. */
+ * variables reproduce; out[9] the k_pblock task order (consecutive block
+ * groups of one state before the next element) and out[10] its request
+ * (0 = 1; CHFPE_TUNE_PB_RUN).  Writes min(n, 11) values and returns that
+ * count. */
 int chfpe_tile_config(const chfpe_ctx *ctx, int32_t *out, int32_t n);
 
 /* ---- Learned per-axis closure (coarse grids) -------------------------------

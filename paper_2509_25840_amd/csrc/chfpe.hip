@@ -279,7 +279,7 @@ int pad8(int n) { return (n + 7) / 8 * 8; }
 // Tile shapes the autotuner picked, kept per problem shape for the rest of
 // the process (later contexts of the same shape start from them).
 struct TileChoice {
-  int pb_nb = 0, pb_split = -1, q_pc = 0;
+  int pb_nb = 0, pb_split = -1, q_pc = 0, pb_run = 0;
 };
 std::mutex g_tune_mu;
 std::map<std::vector<long long>, TileChoice> g_tuned;
@@ -327,6 +327,7 @@ struct chfpe_ctx {
   int tune_pb_nb = 0;   // blocks per k_pblock task (0: automatic)
   int tune_q_pc = 0;    // run positions per two-axis k_qpass tile (0: automatic)
   int tune_pb_split = -1;  // k_pblock lines solved by lane pairs (-1: automatic)
+  int tune_pb_run = 0;     // k_pblock consecutive block groups per state in task order (0: 1)
   bool capturing = false;  // a HIP graph is being captured: no event timing
   bool closure_on = false; // right-hand sides use the closure stencil weights (tb.clos)
   bool use_graphs = true;
@@ -597,7 +598,15 @@ bool plan(chfpe_ctx *c) {
   // every thread row index rg + k RG (k < RPT) has an LDS slot
   const int tile_rows = std::max(nb * pb.rows, pb.RG * ln.pb_rpt);
   pb.tileP = tile_rows * (NpM + 1);
-  pb.ntasks = d.ne * ((pb.nblocks + nb - 1) / nb);
+  // task order: runs of `run` consecutive block groups of one state (longer
+  // contiguous reads), the (branch, element) index next; a run that would
+  // push the launch past one dispatch falls back to 1
+  const int ngroups = (pb.nblocks + nb - 1) / nb;
+  const long long nbat = d.batched ? d.B : 1;
+  pb.run = std::max(1, std::min(c->tune_pb_run > 0 ? c->tune_pb_run : 1, ngroups));
+  auto pb_tasks = [&](int run) { return (long long)d.ne * ((ngroups + run - 1) / run) * run; };
+  if (grid_items(pb_tasks(pb.run) * nbat, pb.RG * pb.cols) > kMaxGridItems) pb.run = 1;
+  pb.ntasks = (int)pb_tasks(pb.run);
   pb.nblk = pad8(pb.ntasks);
   ln.pb_lds = (size_t)pb.NB * pb.tileP * sizeof(double);
   ln.pb_threads = pb.RG * pb.cols;
@@ -623,7 +632,6 @@ bool plan(chfpe_ctx *c) {
     ln.has_qx = true;
     plan_one(c, M + 0, plane, {0, 1, 2}, ln.qx, ln.qx_threads, ln.qx_nmax);
   }
-  const long long nbat = d.batched ? d.B : 1;
   auto fits = [&](const QPass &q, int thr) { return grid_items((long long)q.ntasks * nbat, thr) <= kMaxGridItems; };
   return fits(ln.qf, ln.qf_threads) && (!ln.has_qa || fits(ln.qa, ln.qa_threads)) &&
          (!ln.has_qx || fits(ln.qx, ln.qx_threads));
@@ -1279,11 +1287,13 @@ int chfpe_setup(const chfpe_params *p, void *dev_workspace, size_t ws_bytes, voi
       c->tune_pb_nb = it->second.pb_nb;
       c->tune_pb_split = it->second.pb_split;
       c->tune_q_pc = it->second.q_pc;
+      c->tune_pb_run = it->second.pb_run;
     }
   }
   if (const char *v = std::getenv("CHFPE_TUNE_PB_NB")) c->tune_pb_nb = std::atoi(v);
   if (const char *v = std::getenv("CHFPE_TUNE_Q_PC")) c->tune_q_pc = std::atoi(v);
   if (const char *v = std::getenv("CHFPE_TUNE_PB_SPLIT")) c->tune_pb_split = std::atoi(v);
+  if (const char *v = std::getenv("CHFPE_TUNE_PB_RUN")) c->tune_pb_run = std::atoi(v);
   if (const char *v = std::getenv("CHFPE_NO_GRAPH")) c->use_graphs = std::atoi(v) == 0;
   std::vector<double> F, Vp, pm, pg, sq, sp, wp, cc, tc, damp;
   std::vector<int> up, dn;
@@ -1309,6 +1319,7 @@ int chfpe_setup(const chfpe_params *p, void *dev_workspace, size_t ws_bytes, voi
     c->tune_pb_nb = 0;
     c->tune_pb_split = -1;
     c->tune_q_pc = 0;
+    c->tune_pb_run = 0;
     if (!plan(c)) {
       chfpe_destroy(c);
       return fail(nullptr, CHFPE_EINVAL,
@@ -1641,12 +1652,13 @@ int chfpe_autotune(chfpe_ctx *c, int32_t n_steps) {
   const int timing = c->timing_every;
   c->timing_every = 0;
   const double dt = 1e-3;
-  TileChoice best{c->tune_pb_nb, c->tune_pb_split, c->tune_q_pc};
+  TileChoice best{c->tune_pb_nb, c->tune_pb_split, c->tune_q_pc, c->tune_pb_run};
   double best_ms = 1e300;
   auto restore = [&](int rc) {
     c->tune_pb_nb = best.pb_nb;
     c->tune_pb_split = best.pb_split;
     c->tune_q_pc = best.q_pc;
+    c->tune_pb_run = best.pb_run;
     (void)plan(c);  // the starting shape, or one that fit when timed
     c->timing_every = timing;
     return rc;
@@ -1655,8 +1667,9 @@ int chfpe_autotune(chfpe_ctx *c, int32_t n_steps) {
     c->tune_pb_nb = t.pb_nb;
     c->tune_pb_split = t.pb_split;
     c->tune_q_pc = t.q_pc;
+    c->tune_pb_run = t.pb_run;
     if (!plan(c)) return CHFPE_OK;  // too large a launch for one dispatch: not a candidate
-    const std::vector<int> eff = {c->ln.pb.nb, c->ln.pb.split, c->ln.qf.pc, c->ln.qa.pc};
+    const std::vector<int> eff = {c->ln.pb.nb, c->ln.pb.split, c->ln.qf.pc, c->ln.qa.pc, c->ln.pb.run};
     for (const auto &s : seen)
       if (s == eff) return CHFPE_OK;  // same launches as a shape already timed
     seen.push_back(eff);
@@ -1668,14 +1681,21 @@ int chfpe_autotune(chfpe_ctx *c, int32_t n_steps) {
     }
     return CHFPE_OK;
   };
-  // k_pblock shapes first (q tiles automatic), then q tiles with the best
+  // k_pblock shapes first (q tiles automatic), then q tiles with the best,
+  // then the k_pblock task order
   std::vector<std::vector<int>> seen;
   for (int split : {1, 0})
     for (int nb : {1, 2, 4, 8})
-      if (trial(TileChoice{nb, split, best.q_pc}, seen)) return restore(fail(c, CHFPE_EDEVICE, "autotune step failed"));
+      if (trial(TileChoice{nb, split, best.q_pc, best.pb_run}, seen))
+        return restore(fail(c, CHFPE_EDEVICE, "autotune step failed"));
   const TileChoice pbest = best;
   for (int pc : {4, 8, 16, 32})
-    if (trial(TileChoice{pbest.pb_nb, pbest.pb_split, pc}, seen)) return restore(fail(c, CHFPE_EDEVICE, "autotune step failed"));
+    if (trial(TileChoice{pbest.pb_nb, pbest.pb_split, pc, pbest.pb_run}, seen))
+      return restore(fail(c, CHFPE_EDEVICE, "autotune step failed"));
+  const TileChoice qbest = best;
+  for (int run : {1, 4, 8, 16, 32})
+    if (trial(TileChoice{qbest.pb_nb, qbest.pb_split, qbest.q_pc, run}, seen))
+      return restore(fail(c, CHFPE_EDEVICE, "autotune step failed"));
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned[tune_key(d)] = best;
@@ -1685,10 +1705,10 @@ int chfpe_autotune(chfpe_ctx *c, int32_t n_steps) {
 
 int chfpe_tile_config(const chfpe_ctx *c, int32_t *out, int32_t n) {
   if (!c || !out || n < 0) return CHFPE_EINVAL;
-  const int32_t v[9] = {c->ln.pb.nb,  c->ln.pb.split,    c->ln.pb_threads,
-                        c->ln.qf.pc,  c->ln.has_qa ? c->ln.qa.pc : 0, c->ln.qf_threads,
-                        c->tune_pb_nb, c->tune_pb_split, c->tune_q_pc};
-  const int k = n < 9 ? n : 9;
+  const int32_t v[11] = {c->ln.pb.nb,  c->ln.pb.split,    c->ln.pb_threads,
+                         c->ln.qf.pc,  c->ln.has_qa ? c->ln.qa.pc : 0, c->ln.qf_threads,
+                         c->tune_pb_nb, c->tune_pb_split, c->tune_q_pc, c->ln.pb.run, c->tune_pb_run};
+  const int k = n < 11 ? n : 11;
   for (int i = 0; i < k; ++i) out[i] = v[i];
   return k;
 }

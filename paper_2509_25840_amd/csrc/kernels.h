@@ -324,6 +324,8 @@ struct PBlock {
   int RG;            // row groups; threads = cols * RG
   int tileP;         // padded values of one LDS field = nb * rows * (cols + 1)
   int split;         // 1: two lanes per line (compact_split) where the line length allows
+  int run;           // task order: `run` consecutive block groups of one state, then the
+                     // next (branch, element); tasks past the last block exit
   int ntasks, nblk;
 };
 
@@ -380,10 +382,13 @@ k_pblock(const Geom g, const Tabs tb, const PBlock pb, const T *__restrict__ X, 
   constexpr int sa = MM - 1;  // row axis
   constexpr int sb = MM - 2;  // column axis (NB == 2)
   const int ne_all = g.ne * g.nbatch;
-  const int ea = task % ne_all;   // (branch, element)
+  const int jr = task % pb.run;
+  const int t2 = task / pb.run;
+  const int ea = t2 % ne_all;  // (branch, element)
   const int br = ea / g.ne;
   const int e = ea - br * g.ne;
-  const int b0 = (task / ne_all) * pb.nb;
+  const int b0 = ((t2 / ne_all) * pb.run + jr) * pb.nb;
+  if (b0 >= pb.nblocks) return;  // padding of the last run (whole workgroup)
   const int nbt = min(pb.nb, pb.nblocks - b0);
   const int rows = pb.rows, cols = pb.cols, cp = pb.cols + 1;
   const int nrows = nbt * rows;

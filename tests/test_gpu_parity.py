@@ -348,6 +348,7 @@ TILE_CANDIDATES = [
     {"CHFPE_TUNE_PB_NB": "1"}, {"CHFPE_TUNE_PB_NB": "2"}, {"CHFPE_TUNE_PB_NB": "8"},
     {"CHFPE_TUNE_PB_SPLIT": "0"},
     {"CHFPE_TUNE_Q_PC": "4"}, {"CHFPE_TUNE_Q_PC": "8"}, {"CHFPE_TUNE_Q_PC": "32"},
+    {"CHFPE_TUNE_PB_RUN": "4"}, {"CHFPE_TUNE_PB_RUN": "32"},
 ]
 
 
@@ -359,7 +360,7 @@ def test_every_autotuner_tile_shape_matches_the_oracle(pk, monkeypatch, name):
     ref = orc.rk4(w, W, 2, 0.002)
     bad = []
     for env in TILE_CANDIDATES:
-        for k in ("CHFPE_TUNE_PB_NB", "CHFPE_TUNE_PB_SPLIT", "CHFPE_TUNE_Q_PC"):
+        for k in ("CHFPE_TUNE_PB_NB", "CHFPE_TUNE_PB_SPLIT", "CHFPE_TUNE_Q_PC", "CHFPE_TUNE_PB_RUN"):
             monkeypatch.delenv(k, raising=False)
         for k, v in env.items():
             monkeypatch.setenv(k, v)
