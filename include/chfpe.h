@@ -232,7 +232,10 @@ int chfpe_kernel_times(chfpe_ctx *ctx, int32_t max_kinds, int64_t *counts, doubl
  * shapes (blocks per task 1, 2, 4, 8 where the block fits, with and
  * without lane-pair line solves), then the q-pass tile widths 4, 8, 16, 32
  * (positions of the contiguous run per two-axis tile, as LDS allows) with
- * the best k_pblock shape.  The path timed is the one the context spends
+ * the best k_pblock shape, then the k_pblock task order (runs of 1, 4, 8,
+ * 16, 32 consecutive block groups of one state before the next element).
+ * Candidates whose launch would exceed one dispatch are skipped.  Every
+ * candidate computes the same result.  The path timed is the one the context spends
  * most time in: the batched branch buffers (branch type) when batch > 1,
  * else the FP64 single-state path.  The fastest shape is kept by this
  * context and, for the rest of the process, by every later context of the
