@@ -168,10 +168,13 @@ def test_training_steps_match_the_oracle_and_reduce_the_loss(pk):
     assert more[-1] < 0.9 * loss[0]
 
 
+@pytest.mark.parametrize("run", ["0", "3"])
 @pytest.mark.parametrize("name", list(COARSE))
-def test_coarse_solver_with_closure_matches_the_oracle(pk, name):
+def test_coarse_solver_with_closure_matches_the_oracle(pk, monkeypatch, name, run):
+    # run: k_pblock task order (consecutive block groups per state; 0 = default)
+    monkeypatch.setenv("CHFPE_TUNE_PB_RUN", run)
     w = COARSE[name]
-    say(f"[closure solver] {name}")
+    say(f"[closure solver] {name} run {run}")
     n = len(cl.features(w))
     sv = np.random.default_rng(9).normal(0, 0.02, n)
     W = phys_state(w, seed=12)
