@@ -329,6 +329,7 @@ def main(argv=None):
     ap.add_argument("--bench-json", help="summarise: the JSON line the traced bench run printed")
     ap.add_argument("--kernels-json", help="summarise: the JSON line the counted kernels run printed")
     ap.add_argument("--rk4-steps", type=int, default=4, help="RK4 steps in --mode kernels")
+    ap.add_argument("--tune", action="store_true", help="rk4: autotune the tile shapes first")
     args = ap.parse_args(argv)
     if args.mode == "summarise":
         return summarise(args)
@@ -382,6 +383,7 @@ def main(argv=None):
     if args.mode == "rk4":
         # time RK4 propagation alone (tile sweeps); one JSON line per call
         solver.equilibrate(0, 0.0)
+        tiles = solver.autotune(2) if args.tune else solver.tile_config()
         solver.propagate(20, dt)
         torch.cuda.synchronize()
         solver.set_kernel_timing(8)
@@ -395,6 +397,7 @@ def main(argv=None):
                           "updates_per_s": S * args.rk4_steps / el,
                           "alg_frac_16pass": 16 * 8 * S * args.rk4_steps / el / 1e9 / HBM_PEAK_GBPS,
                           "env": {k: v for k, v in os.environ.items() if k.startswith("CHFPE_TUNE")},
+                          "tiles": tiles,
                           "kernels": {k: {"ms": v[1], "GBps": v[2] / (v[1] * 1e-3) / 1e9}
                                       for k, v in kt.items() if v[0] > 0}}), flush=True)
         solver.close()
