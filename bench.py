@@ -237,6 +237,13 @@ def summarise(args) -> int:
             rec["fetch_bytes_per_launch"][kind] = fb
             rec["write_bytes_per_launch"][kind] = wb
             rec["bytes_per_launch"][kind] = fb + wb
+        if args.traffic_variant:
+            # another tile choice of the same kernels: its record only, beside the main one
+            tag = args.tiles.replace(",", "_")
+            path = os.path.join(ROOT, "profiles", f"traffic_{args.workload}_tiles_{tag}.json")
+            json.dump(rec, open(path, "w"), indent=1)
+            log(f"[summarise] wrote {path}")
+            return 0
         path = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
         json.dump(rec, open(path, "w"), indent=1)
         lines = [f"# HBM traffic per launch: {args.workload}, {args.precision} branch states, "
@@ -328,6 +335,8 @@ def main(argv=None):
     ap.add_argument("--write-dir", help="summarise: rocprofv3 --pmc WRITE_SIZE output folder")
     ap.add_argument("--bench-json", help="summarise: the JSON line the traced bench run printed")
     ap.add_argument("--kernels-json", help="summarise: the JSON line the counted kernels run printed")
+    ap.add_argument("--traffic-variant", action="store_true",
+                    help="summarise: write only a tile-specific traffic record (traffic_<workload>_tiles_<tiles>.json)")
     ap.add_argument("--rk4-steps", type=int, default=4, help="RK4 steps in --mode kernels")
     ap.add_argument("--tune", action="store_true", help="rk4: autotune the tile shapes first")
     args = ap.parse_args(argv)
@@ -675,17 +684,22 @@ def main(argv=None):
         dom = max(share, key=share.get)
         mean_ms = kt[dom][1]
         achieved = kb[dom] / (mean_ms * 1e-3) / 1e9
+        # counter-measured bytes of the same kernels, batch, precision and tile
+        # choice (the main record or a tile-specific one), else null
         traffic = None
-        tf = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
-        if os.path.exists(tf):
+        prof = os.path.join(ROOT, "profiles")
+        names = sorted(f for f in os.listdir(prof) if f.startswith(f"traffic_{args.workload}")
+                       and f.endswith(".json")) if os.path.isdir(prof) else []
+        for name in names:
             try:
-                rec = json.load(open(tf))
-                if (rec.get("source_hash") == source_hash() and dom in rec.get("bytes_per_launch", {})
-                        and rec.get("batch") == args.batch and rec.get("precision") == args.precision
-                        and rec.get("tiles") in ("", tiles_arg)):
-                    traffic = float(rec["bytes_per_launch"][dom])
+                rec = json.load(open(os.path.join(prof, name)))
             except (OSError, ValueError):
-                traffic = None
+                continue
+            if (rec.get("source_hash") == source_hash() and dom in rec.get("bytes_per_launch", {})
+                    and rec.get("batch") == args.batch and rec.get("precision") == args.precision
+                    and rec.get("tiles") in ("", tiles_arg)):
+                traffic = float(rec["bytes_per_launch"][dom])
+                break
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                     "traffic": traffic, "mean_ms": mean_ms, "bytes_per_launch": kb[dom],
