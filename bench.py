@@ -143,6 +143,25 @@ def _cmd(args, extra: str) -> str:
             f"--precision {args.precision}" + (f" --tiles {args.tiles}" if args.tiles else ""))
 
 
+def recorded_traffic(workload: str, batch: int, precision: str, tiles: str, kind: str,
+                     prof: str = os.path.join(ROOT, "profiles")):
+    """Counter-measured HBM bytes per launch of `kind` from a traffic record
+    of the same kernel sources, batch, precision and tile choice (the main
+    record or a tile-specific one), else None."""
+    names = sorted(f for f in os.listdir(prof) if f.startswith(f"traffic_{workload}")
+                   and f.endswith(".json")) if os.path.isdir(prof) else []
+    for name in names:
+        try:
+            rec = json.load(open(os.path.join(prof, name)))
+        except (OSError, ValueError):
+            continue
+        if (rec.get("source_hash") == source_hash() and kind in rec.get("bytes_per_launch", {})
+                and rec.get("batch") == batch and rec.get("precision") == precision
+                and rec.get("tiles") in ("", tiles)):
+            return float(rec["bytes_per_launch"][kind])
+    return None
+
+
 def summarise(args) -> int:
     tag = f"{args.workload}_{args.precision}_b{args.batch}"
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
@@ -684,22 +703,7 @@ def main(argv=None):
         dom = max(share, key=share.get)
         mean_ms = kt[dom][1]
         achieved = kb[dom] / (mean_ms * 1e-3) / 1e9
-        # counter-measured bytes of the same kernels, batch, precision and tile
-        # choice (the main record or a tile-specific one), else null
-        traffic = None
-        prof = os.path.join(ROOT, "profiles")
-        names = sorted(f for f in os.listdir(prof) if f.startswith(f"traffic_{args.workload}")
-                       and f.endswith(".json")) if os.path.isdir(prof) else []
-        for name in names:
-            try:
-                rec = json.load(open(os.path.join(prof, name)))
-            except (OSError, ValueError):
-                continue
-            if (rec.get("source_hash") == source_hash() and dom in rec.get("bytes_per_launch", {})
-                    and rec.get("batch") == args.batch and rec.get("precision") == args.precision
-                    and rec.get("tiles") in ("", tiles_arg)):
-                traffic = float(rec["bytes_per_launch"][dom])
-                break
+        traffic = recorded_traffic(args.workload, args.batch, args.precision, tiles_arg, dom)
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                     "traffic": traffic, "mean_ms": mean_ms, "bytes_per_launch": kb[dom],
