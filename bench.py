@@ -20,6 +20,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -35,11 +36,27 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def source_hash() -> str:
+KERNEL_SOURCES = ("paper_2509_25840_amd/csrc/kernels.h", "paper_2509_25840_amd/csrc/closure.h",
+                  "paper_2509_25840_amd/csrc/chfpe.hip")
+
+
+def code_of(text: str) -> str:
+    """Source text without comments, trailing blanks and empty lines: what the
+    compiler sees, so that comment edits leave recorded profiles valid."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
+def source_hash(read=None) -> str:
+    """Hash of the kernel sources' code; profiles record it and bench.py uses a
+    profile only while it matches.  `read(rel)` returns a source's text
+    (default: the working tree)."""
+    if read is None:
+        read = lambda rel: open(os.path.join(ROOT, rel), encoding="utf-8").read()
     h = hashlib.sha256()
-    for rel in ("paper_2509_25840_amd/csrc/kernels.h", "paper_2509_25840_amd/csrc/chfpe.hip"):
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+    for rel in KERNEL_SOURCES:
+        h.update(code_of(read(rel)).encode())
     return h.hexdigest()[:16]
 
 
@@ -279,8 +296,8 @@ def summarise(args) -> int:
             lines.append(f"| {kind} | {per[kind]['fetch'][0]} | {rec['fetch_bytes_per_launch'][kind] / 1e6:.2f} | "
                          f"{rec['write_bytes_per_launch'][kind] / 1e6:.2f} | {t / 1e6:.2f} | "
                          f"{'%.2f' % (a / 1e6) if a else '-'} | {'%.3f' % (t / a) if a else '-'} |")
-        lines += ["", f"Kernel sources hash: {rec['source_hash']} (bench.py uses these figures only while "
-                  f"the kernel sources hash to this value)."]
+        lines += ["", f"Kernel sources hash: {rec['source_hash']} (of their code, comments excluded; bench.py "
+                  f"uses these figures only while the kernel sources hash to this value)."]
         path = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.md")
         open(path, "w").write("\n".join(lines) + "\n")
         log(f"[summarise] wrote {path}")

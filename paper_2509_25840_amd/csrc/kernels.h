@@ -9,25 +9,28 @@
 // The right-hand side is split by axis family so that every compact
 // derivative (Sec. III B) sees whole lines:
 //
-//   k_pblock  -- for every element n and a run of q points, the whole
-//                p-block (all p_1..p_M values, contiguous in memory) is staged
-//                through LDS.  It forms the field the p_s derivative acts on,
+//   k_pblock  -- for every element n, blocks of the innermost p axes (p_M,
+//                and p_{M-1} for two or three modes; contiguous in memory)
+//                are staged through LDS.  It forms the field the p_s
+//                derivative acts on,
 //                  G_{n,s} = F_s W_n + V_s' W_{n+e_s} + n_s zeta_s gamma_s (m_s/beta) V_s' W_{n-e_s},
-//                solves every p_s line (Thomas, line held in registers) and
-//                adds the pointwise terms
+//                solves those p_s lines (Thomas from both ends, two lanes per
+//                line, streamed through LDS) and adds the pointwise terms
 //                  sum_s V_s' p_s [ (n_s zeta_s gamma_s/2) h_{n-e_s} - (beta/2m_s) h_{n+e_s} ]
 //                  - sum_s n_s gamma_s h_n.
 //                D_p(F W) = F D_p W and D_p(V' W) = V' D_p W because F_s and
 //                V_s' do not depend on p_s, so one solve per (n, s) covers the
-//                Liouvillian, Phi and the derivative part of Theta.
+//                Liouvillian, Phi and the derivative part of Theta.  For
+//                three modes the p_1 derivative of G_{n,1} is taken by a
+//                k_qpass over (q_1, p_1), which forms that field itself.
 //   k_qpass   -- the -(p_s/m_s) D_{q_s} W_n terms.  A tile is one or two
 //                q axes at full length times a chunk of consecutive p-block
 //                positions; each thread holds one q_a line in registers, a
 //                second q_b axis goes through LDS.  The last q pass of a
 //                stage also applies the classical RK4 stage update.
 //
-// All state arithmetic is in the template type T (double here); tables and
-// reductions are FP64.
+// All state arithmetic is in the template type T (double, or float for FP32
+// branch states); tables and reductions are FP64.
 #pragma once
 
 #include <hip/hip_runtime.h>

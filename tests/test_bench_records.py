@@ -27,3 +27,16 @@ def test_stale_or_broken_records_are_ignored(tmp_path):
     (tmp_path / "traffic_w_tiles_1_1_0_1.json").write_text(json.dumps(rec))
     assert bench.recorded_traffic("w", 2, "f64", "1,1,0,1", "k", prof=str(tmp_path)) == 123.0
     assert bench.recorded_traffic("w", 2, "f64", "1,1,0,1", "other", prof=str(tmp_path)) is None
+
+
+def test_source_hash_follows_code_not_comments():
+    base = {rel: open(f"{bench.ROOT}/{rel}", encoding="utf-8").read() for rel in bench.KERNEL_SOURCES}
+    h0 = bench.source_hash(lambda rel: base[rel])
+    assert h0 == bench.source_hash()
+    rel = bench.KERNEL_SOURCES[0]
+    commented = dict(base)
+    commented[rel] = "// a new comment\n/* and a block\n   comment */\n" + base[rel].replace("\n", "  // note\n", 3)
+    assert bench.source_hash(lambda r: commented[r]) == h0
+    changed = dict(base)
+    changed[rel] = base[rel] + "\nconstexpr int kProbe = 1;\n"
+    assert bench.source_hash(lambda r: changed[r]) != h0
