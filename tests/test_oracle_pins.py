@@ -11,7 +11,7 @@ import oracle as orc
 import workloads as wl
 from oracle import dense
 from physics_refs import (boltzmann_average_1d, chi_brownian, linear_response_1d,
-                          lyapunov_moments)
+                          lyapunov_moments, response_2d_gaussian)
 
 
 def harmonic_ll(N=48, K=2, **kw):
@@ -384,6 +384,157 @@ def test_second_order_response_parity_zero():
     R1 = orc.response_2d(w, lin, quadB, lin, Wb, 3, 4, 3, 3, 0.005)
     assert np.abs(R1).max() > 1e-6
     assert np.abs(R0).max() < 1e-12 * np.abs(R1).max()
+
+
+def _potential_np(w, Q):
+    """U(q) of the model (Sec. II A, with the quartic on-site term) on arrays."""
+    M = w["M"]
+    U = 0.0
+    for s in range(M):
+        x = Q[s]
+        U = U + 0.5 * w["m"][s] * w["omega"][s] ** 2 * x ** 2 + w["g3"][s] * x ** 3 / 6 + w["g4"][s] * x ** 4 / 24
+        for t in range(s + 1, M):
+            y = Q[t]
+            U = U + w["g2"][s][t] * x * y + (w["g21"][s][t] * x * x * y + w["g12"][s][t] * x * y * y) / 6
+    return U
+
+
+def _boltzmann_average(w, f, n):
+    """<f(q)> under exp(-beta U) over the q box, tensor Gauss-Legendre with n
+    nodes per axis (independent of the oracle's grid and quadrature)."""
+    M = w["M"]
+    nodes, wts = [], []
+    for s in range(M):
+        x, wt = np.polynomial.legendre.leggauss(n)
+        nodes.append(x * w["Lq"][s])
+        wts.append(wt * w["Lq"][s])
+    Q = np.meshgrid(*nodes, indexing="ij")
+    Wt = np.ones_like(Q[0])
+    for s in range(M):
+        shape = [1] * M
+        shape[s] = n
+        Wt = Wt * wts[s].reshape(shape)
+    b = Wt * np.exp(-w["beta"] * _potential_np(w, Q))
+    return float((b * f(Q)).sum() / b.sum())
+
+
+def _dX(X, s, Q):
+    M = len(Q)
+    return X["lin"][s] + sum(0.5 * (X["quad"][s][t] + X["quad"][t][s]) * Q[t] for t in range(M))
+
+
+_X2 = wl.optical(2, lin=[1.0, 0.7], quad=[[0.2, 0.1], [0.1, -0.3]])
+_X3 = wl.optical(3, lin=[1.0, 0.7, 0.5], quad=[[0.2, 0.1, 0.05], [0.1, -0.3, 0.08], [0.05, 0.08, 0.1]])
+
+
+@pytest.mark.parametrize("M", [2, 3])
+def test_linear_response_slope_sum_rule_multimode(M):
+    """dR^(1)/dt(0) = -sum_s <(dA/dq_s)^2>_Boltzmann / m_s for anharmonic,
+    coupled modes and an operator with cross terms quad_ss' q_s q_s'
+    (Eqs. (Opticalexc), (1Dresponse)); the reference is a Gauss-Legendre
+    average over the q box, and the oracle converges to it at sixth order."""
+    name, X, Ns, K, nq = ("two_mode_32", _X2, (24, 32, 40), 1, 96) if M == 2 else \
+        ("three_mode_24", _X3, (12, 14, 16), 0, 48)
+    w0 = wl.workload(name)
+    ref = -sum(_boltzmann_average(w0, lambda Q, s=s: _dX(X, s, Q) ** 2, nq) / w0["m"][s] for s in range(M))
+    errs, hs = [], []
+    for N in Ns:
+        w = wl.workload(name, Nq=[N] * M, Np=[N] * M, K=K)
+        u = orc.perturb(w, X, orc.boltzmann(w))
+        errs.append(abs(orc.observe(w, X, orc.rhs(w, u)) - ref) / abs(ref))
+        hs.append(1.0 / N)
+    rates, last = order_and_last(errs, hs)
+    assert last < (1e-5 if M == 2 else 3e-3) and np.all(rates > 5.5), (errs, rates)
+
+
+@pytest.mark.parametrize("M", [2, 3])
+def test_excitation_acts_on_every_element(M):
+    """X^x acts on every hierarchy element (Eq. (Opticalexc) on the full
+    density, whose f-moments are the elements): for each n and s,
+    int p_s (X^x W)_n = -int dX/dq_s W_n, by parts in p.  The identity holds
+    at every q point, so q stays coarse and p is refined; the error falls at
+    sixth order.  An excitation of element 0 alone fails it for n >= 1."""
+    name, X, Nq, Ns = ("two_mode_32", _X2, [6, 5], (24, 32, 40)) if M == 2 else \
+        ("three_mode_24", _X3, [4, 3, 5], (16, 20, 24))
+    errs, hs = [], []
+    for N in Ns:
+        w = wl.workload(name, Nq=Nq, Np=[N] * M, K=1)
+        axes = [-w["Lq"][s] + (np.arange(w["Nq"][s]) + 0.5) * 2 * w["Lq"][s] / w["Nq"][s] for s in range(M)]
+        axes += [-w["Lp"][s] + (np.arange(N) + 0.5) * 2 * w["Lp"][s] / N for s in range(M)]
+        G = np.meshgrid(*axes, indexing="ij")
+        Wb = orc.boltzmann(w)[0]
+        W = np.zeros(orc.state_shape(w))
+        rng = np.random.default_rng(4)
+        for n in range(W.shape[0]):
+            c = rng.uniform(-0.5, 0.5, size=2 * M)
+            W[n] = Wb * (0.5 + n + sum(c[k] * G[k] for k in range(2 * M)) + 0.1 * G[M] * G[-1])
+        u = orc.perturb(w, X, W)
+        e = []
+        for n in range(W.shape[0]):
+            for s in range(M):
+                lhs = orc.moments(w, u, n, s)[2]
+                rhs = -(X["lin"][s] * orc.moments(w, W, n, s)[0]
+                        + sum(0.5 * (X["quad"][s][t] + X["quad"][t][s]) * orc.moments(w, W, n, t)[1]
+                              for t in range(M)))
+                e.append(abs(lhs - rhs) / abs(rhs))
+        errs.append(max(e))
+        hs.append(1.0 / N)
+    rates, last = order_and_last(errs, hs)
+    assert last < (5e-6 if M == 2 else 1e-4) and np.all(rates > 5.5), (errs, rates)
+
+
+def _harmonic_ll_w(N, K):
+    return wl.workload("one_mode_48", Nq=[N], Np=[N], K=K, g3=[0.0], g4=[0.0], VSL=[0.0])
+
+
+@pytest.mark.parametrize("case", ["quadB_K3", "linB_quadC_K2"])
+def test_second_order_response_gaussian_closed_form(case):
+    """The whole double loop of Eq. (2Dresponse) against a closed form.  For a
+    harmonic mode with linear-linear coupling the density stays polynomial x
+    P_eq(q, p, f), so R^(2) is a Gaussian expectation (tests/physics_refs.py).
+    B^x then acts on hierarchy elements n >= 1 of G(t1) A^x W_eq, which are
+    nonzero.  Quadratic B gives a cubic density (exact at depth 3); linear B
+    with quadratic C a quadratic one (exact at depth 2).  Sixth-order
+    convergence at two sets of strides; exciting element 0 alone misses by
+    ~7e-3 at every N."""
+    if case == "quadB_K3":
+        A, B, C = wl.optical(1, lin=[1.0]), wl.optical(1, lin=[0.5], quad=[[0.6]]), \
+            wl.optical(1, lin=[1.0], quad=[[0.2]])
+        K, n1, n2, s1, s2 = 3, 4, 5, 40, 40
+    else:
+        A, B, C = wl.optical(1, lin=[1.0]), wl.optical(1, lin=[0.8]), wl.optical(1, lin=[0.3], quad=[[0.5]])
+        K, n1, n2, s1, s2 = 2, 3, 4, 25, 60
+    dt = 0.005
+    ref = response_2d_gaussian(_harmonic_ll_w(48, K), A, B, C, np.arange(n1) * s1 * dt, np.arange(n2) * s2 * dt)
+    assert np.abs(ref).max() > 1e-2
+    errs, hs = [], []
+    for N in (32, 40, 48):
+        w = _harmonic_ll_w(N, K)
+        R = orc.response_2d(w, A, B, C, orc.boltzmann(w), n1, n2, s1, s2, dt)
+        errs.append(np.abs(R - ref).max() / np.abs(ref).max())
+        hs.append(1.0 / N)
+    rates, last = order_and_last(errs, hs)
+    assert last < 1e-5 and np.all(rates > 5.5), (errs, rates)
+
+
+def test_second_order_response_gaussian_closed_form_two_modes():
+    """Two harmonic modes with a bilinear coupling and their own Drude baths,
+    B with a cross term Pi_12 q_1 q_2: R^(2) against the Gaussian closed form.
+    Depth 2 (the depth-3 terms move R by ~1e-10 here).  The p grid converges
+    slowly (Sec. III A), so the check is the error at N = 20 and its
+    sixth-order fall from N = 16."""
+    A = wl.optical(2, lin=[1.0, 0.6])
+    B = wl.optical(2, lin=[0.4, 0.3], quad=[[0.5, 0.3], [0.3, -0.2]])
+    C = wl.optical(2, lin=[1.0, 0.6])
+    n1, n2, s1, s2, dt = 2, 3, 10, 10, 0.02
+    errs = []
+    for N in (16, 20):
+        w = wl.workload("two_mode_32", Nq=[N, N], Np=[N, N], K=2, g3=[0.0, 0.0], g4=[0.0, 0.0], VSL=[0.0, 0.0])
+        w["g2"][0][1] = 0.3
+        ref = response_2d_gaussian(w, A, B, C, np.arange(n1) * s1 * dt, np.arange(n2) * s2 * dt)
+        R = orc.response_2d(w, A, B, C, orc.boltzmann(w), n1, n2, s1, s2, dt)
+        errs.append(np.abs(R - ref).max() / np.abs(ref).max())
+    assert errs[1] < 3e-3 and errs[0] / errs[1] > (20 / 16) ** 5.5, errs
 
 
 # ---------------------------------------------------------------------------
