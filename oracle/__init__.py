@@ -6,7 +6,8 @@ library and its binding) never calls it.
 
 The arithmetic lives in ``chfpe_oracle.c`` (plain C, FP64, OpenMP over grid
 lines); this module marshals arguments with ctypes and adds the spectra of
-Eqs. (1DIR_Raman) and (2DThz_Raman) as plain discrete Fourier sums.
+Eqs. (1DIR_Raman), (2DThz_Raman) and (noncorrelation) as plain discrete
+Fourier sums.
 It shares no code with the HIP path; inputs come from ``workloads``.
 """
 from __future__ import annotations
@@ -93,6 +94,9 @@ def _load():
     lib.orc_response_2d.argtypes = [P, O, O, O, dp, i64, i64, ctypes.c_int, ctypes.c_int,
                                     ctypes.c_double, ctypes.POINTER(i64), i64, dp]
     lib.orc_response_2d.restype = None
+    lib.orc_response_3d.argtypes = [P, O, O, O, O, dp, i64, i64, i64, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_double, ctypes.POINTER(i64), i64, dp]
+    lib.orc_response_3d.restype = None
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -265,8 +269,28 @@ def response_2d(w: dict, A: dict, B: dict, C: dict, Weq, n_t1: int, n_t2: int,
     return R
 
 
+def response_3d(w: dict, A: dict, B: dict, C: dict, D: dict, Weq, n_t1: int, t2_steps: int, n_t3: int,
+                stride1: int, stride3: int, dt: float, j1_list=None) -> np.ndarray:
+    """R^(3)[j3, j1] of Eq. (3Dresponse) at the waiting time t2 = t2_steps * dt;
+    shape (n_t3, n_t1), t1 fastest.  With ``j1_list`` only those t1 columns
+    are computed (others are NaN)."""
+    Weq = _state(w, Weq)
+    R = np.full((int(n_t3), int(n_t1)), np.nan)
+    ops = [optical(X) for X in (A, B, C, D)]
+    if j1_list is None:
+        jl, nj = None, 0
+    else:
+        arr = np.ascontiguousarray(sorted(int(j) for j in j1_list), dtype=np.int64)
+        jl, nj = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), arr.size
+    _load().orc_response_3d(ctypes.byref(params(w)), *[ctypes.byref(o) for o in ops], _ptr(Weq),
+                            int(n_t1), int(t2_steps), int(n_t3), int(stride1), int(stride3), float(dt),
+                            jl, int(nj), _ptr(R))
+    return R
+
+
 # ---------------------------------------------------------------------------
-# spectra, Eqs. (1DIR_Raman) and (2DThz_Raman), as plain Fourier sums
+# spectra, Eqs. (1DIR_Raman), (2DThz_Raman) and (noncorrelation), as plain
+# Fourier sums
 # ---------------------------------------------------------------------------
 
 def spectrum_1d(R, tau: float):
@@ -301,3 +325,22 @@ def spectrum_2d(R, tau1: float, tau2: float):
     omega1 = 2.0 * np.pi * k1 / (n1 * tau1)
     omega2 = 2.0 * np.pi * k2 / (n2 * tau2)
     return omega1, omega2, I
+
+
+def spectrum_2dir(R, tau1: float, tau3: float):
+    """I(omega3, t2, omega1) = Im{ tau1 tau3 sum e^{-i omega1 t1 + i omega3 t3} R(t3, t1) },
+    Eq. (noncorrelation), at the waiting time of R.
+
+    R has shape (n3, n1) with t1 fastest; the result has the same shape,
+    indexed [k3, k1].  Returns (omega1, omega3, I).
+    """
+    R = np.asarray(R, dtype=np.float64)
+    n3, n1 = R.shape
+    k1 = np.arange(n1)
+    k3 = np.arange(n3)
+    E1 = np.exp(-1j * 2.0 * np.pi * np.outer(k1, k1) / n1)  # [k1, j1]
+    E3 = np.exp(+1j * 2.0 * np.pi * np.outer(k3, k3) / n3)  # [k3, j3]
+    I = np.imag(tau1 * tau3 * (E3 @ R @ E1.T))
+    omega1 = 2.0 * np.pi * k1 / (n1 * tau1)
+    omega3 = 2.0 * np.pi * k3 / (n3 * tau3)
+    return omega1, omega3, I

@@ -616,7 +616,7 @@ double orc_energy(const orc_params *P, const double *W) {
 }
 
 /* ------------------------------------------------------------------ */
-/* response functions, Eqs. (1Dresponse), (2Dresponse)                  */
+/* response functions, Eqs. (1Dresponse), (2Dresponse), (3Dresponse)   */
 /* ------------------------------------------------------------------ */
 
 /* R[j] = <A>( G(j*stride*dt) A^x W_eq ),  j = 0..nt-1 */
@@ -658,6 +658,41 @@ void orc_response_2d(const orc_params *P, const orc_optical *A, const orc_optica
   }
   free(u);
   free(v);
+}
+
+/* Third-order response, Eq. (3Dresponse), at one waiting time t2:
+ *   R[j3 * nt1 + j1] = <D>( G(j3*s3*dt) C^x G(t2_steps*dt) B^x G(j1*s1*dt) A^x W_eq )
+ * for the listed t1 indices j1 (all of 0..nt1-1 when j1_list is NULL;
+ * j1_list ascending).  Each branch follows the excitations and free
+ * propagations of the equation from right to left. */
+void orc_response_3d(const orc_params *P, const orc_optical *A, const orc_optical *B,
+                     const orc_optical *C, const orc_optical *D, const double *Weq, int64_t nt1,
+                     int64_t t2_steps, int64_t nt3, int s1, int s3, double dt, const int64_t *j1_list,
+                     int64_t n_j1, double *R) {
+  int64_t S = orc_state_size(P);
+  double *u = (double *)malloc(sizeof(double) * S);
+  double *v = (double *)malloc(sizeof(double) * S);
+  double *x = (double *)malloc(sizeof(double) * S);
+  orc_perturb(P, A, Weq, u);
+  int64_t done = 0; /* t1 steps already applied to u */
+  int64_t count = j1_list ? n_j1 : nt1;
+  for (int64_t c = 0; c < count; ++c) {
+    int64_t j1 = j1_list ? j1_list[c] : c;
+    if (j1 * s1 > done) {
+      orc_rk4(P, u, j1 * s1 - done, dt);
+      done = j1 * s1;
+    }
+    orc_perturb(P, B, u, v);
+    orc_rk4(P, v, t2_steps, dt);
+    orc_perturb(P, C, v, x);
+    for (int64_t j3 = 0; j3 < nt3; ++j3) {
+      if (j3 > 0) orc_rk4(P, x, s3, dt);
+      R[j3 * nt1 + j1] = orc_observe(P, D, x);
+    }
+  }
+  free(u);
+  free(v);
+  free(x);
 }
 
 int orc_num_threads(void) {

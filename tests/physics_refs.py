@@ -270,5 +270,31 @@ def response_2d_gaussian(w, A, B, C, t1s, t2s):
     return R
 
 
+def response_3d_gaussian(w, A, B, C, D, t1s, t2, t3s):
+    """R[j3][j1] = <D>(G(t3_j3) C^x G(t2) B^x G(t1_j1) A^x W_eq), Eq. (3Dresponse),
+    for the linear model: the chain of R^(2) with one more free propagation
+    (the waiting time t2) and one more excitation."""
+    M = w["M"]
+    J = linear_gle_matrix(w)
+    S = stationary_covariance(w)
+    Sinv = np.linalg.inv(S)
+    pA = excite(A, Poly.const(1.0), w)
+    Dp = optical_poly(D, M)
+    d = 3 * M
+    R = np.zeros((len(t3s), len(t1s)))
+    from scipy.linalg import expm as _expm
+    for j1, t1 in enumerate(t1s):
+        g = excite(C, evolve(excite(B, evolve(pA, w, t1, J, S, Sinv), w), w, t2, J, S, Sinv), w)
+        for j3, t3 in enumerate(t3s):
+            E3S = _expm(J * t3) @ S
+            cov = np.zeros((2 * d, 2 * d))
+            cov[:d, :d] = S
+            cov[d:, d:] = S
+            cov[d:, :d] = E3S
+            cov[:d, d:] = E3S.T
+            R[j3, j1] = gauss_expect(Cp_shift(Dp, d) * g, cov)
+    return R
+
+
 def Cp_shift(P, d):
     return Poly({tuple(i + d for i in k): v for k, v in P.t.items()})

@@ -11,7 +11,7 @@ import oracle as orc
 import workloads as wl
 from oracle import dense
 from physics_refs import (boltzmann_average_1d, chi_brownian, linear_response_1d,
-                          lyapunov_moments, response_2d_gaussian)
+                          lyapunov_moments, response_2d_gaussian, response_3d_gaussian)
 
 
 def harmonic_ll(N=48, K=2, **kw):
@@ -537,6 +537,63 @@ def test_second_order_response_gaussian_closed_form_two_modes():
     assert errs[1] < 3e-3 and errs[0] / errs[1] > (20 / 16) ** 5.5, errs
 
 
+@pytest.mark.parametrize("case", ["quad_BD", "quad_BCD"])
+def test_third_order_response_gaussian_closed_form(case):
+    """R^(3)(t3, t2, t1) of Eq. (3Dresponse) for one harmonic mode with
+    linear-linear coupling against the Gaussian closed form, under grid
+    refinement: sixth-order convergence.  With linear operators only, a
+    linear system has no third-order response, and by parity a quadratic B
+    alone leaves R^(3) zero too; the cases have a quadratic B and D, and a
+    quadratic B, C and D.  The hierarchy holds the perturbed density exactly
+    once its depth reaches the density's degree in f: four for a quadratic
+    B and linear C (degrees 1, 3, 4 after A^x, B^x, C^x), five with C
+    quadratic too.  An oracle that excites element 0 only, drops the
+    waiting-time propagation or applies C^x before it misses by O(1)."""
+    if case == "quad_BD":
+        A, B, C, D = (wl.optical(1, lin=[1.0]), wl.optical(1, lin=[0.8], quad=[[0.5]]),
+                      wl.optical(1, lin=[0.6]), wl.optical(1, lin=[1.0], quad=[[0.4]]))
+        K, n1, t2s, n3, s1, s3 = 4, 3, 40, 4, 25, 30
+    else:
+        A, B, C, D = (wl.optical(1, lin=[1.0]), wl.optical(1, lin=[0.5], quad=[[0.4]]),
+                      wl.optical(1, lin=[0.7], quad=[[-0.3]]), wl.optical(1, lin=[1.0], quad=[[0.2]]))
+        K, n1, t2s, n3, s1, s3 = 5, 3, 20, 4, 40, 40
+    dt = 0.005
+    ref = response_3d_gaussian(_harmonic_ll_w(48, K), A, B, C, D, np.arange(n1) * s1 * dt, t2s * dt,
+                               np.arange(n3) * s3 * dt)
+    assert np.abs(ref).max() > 1e-3
+    errs, hs = [], []
+    for N in (40, 48, 56, 64):
+        w = _harmonic_ll_w(N, K)
+        R = orc.response_3d(w, A, B, C, D, orc.boltzmann(w), n1, t2s, n3, s1, s3, dt)
+        errs.append(np.abs(R - ref).max() / np.abs(ref).max())
+        hs.append(1.0 / N)
+    rates, last = order_and_last(errs, hs)
+    # the densities are polynomials of degree 4-5 in (q, p, f): the p grid
+    # resolves them more slowly than R^(2)'s, so the grids run to N = 64
+    # (the oracle has no axis limit) and the bar is the sixth-order fall
+    assert last < 1e-3 and np.all(rates > 5.5), (errs, rates)
+
+
+def test_third_order_response_columns_and_t3_zero():
+    """The listed-column form of R^(3) equals the full one column by column,
+    and R^(3)(t3 = 0) vanishes at the scheme's order (the integral of C^x V
+    against D is a sum of p-derivatives): the t3 = 0 row falls at sixth
+    order from N = 32 to 48, to below 2e-3 of the signal."""
+    A, B, C, D = (wl.optical(1, lin=[1.0], quad=[[0.2]]), wl.optical(1, lin=[0.7], quad=[[0.3]]),
+                  wl.optical(1, lin=[0.9]), wl.optical(1, lin=[1.0], quad=[[0.2]]))
+    zero = []
+    for N in (32, 48):
+        w = _harmonic_ll_w(N, 3)
+        Wb = orc.boltzmann(w)
+        full = orc.response_3d(w, A, B, C, D, Wb, 4, 20, 5, 10, 10, 0.005)
+        zero.append(np.abs(full[0]).max() / np.abs(full).max())
+    part = orc.response_3d(w, A, B, C, D, Wb, 4, 20, 5, 10, 10, 0.005, j1_list=[1, 3])
+    np.testing.assert_array_equal(part[:, [1, 3]], full[:, [1, 3]])
+    assert np.all(np.isnan(part[:, [0, 2]]))
+    rate = np.log(zero[0] / zero[1]) / np.log(48 / 32)
+    assert zero[1] < 2e-3 and rate > 5.5, (zero, rate)
+
+
 # ---------------------------------------------------------------------------
 # spectra, Eqs. (1DIR_Raman), (2DThz_Raman): Fourier sums of known signals
 # ---------------------------------------------------------------------------
@@ -562,3 +619,15 @@ def test_spectrum_2d_against_fft():
     _, _, I = orc.spectrum_2d(R, 0.1, 0.2)
     ref = np.imag(0.1 * 0.2 * np.fft.fft2(R))
     np.testing.assert_allclose(I, ref, rtol=0, atol=1e-12)
+
+
+def test_spectrum_2dir_against_fft():
+    """Eq. (noncorrelation): e^{-i omega1 t1} along t1 (numpy's forward FFT)
+    and e^{+i omega3 t3} along t3 (n3 times its inverse FFT)."""
+    rng = np.random.default_rng(3)
+    R = rng.standard_normal((12, 10))
+    w1, w3, I = orc.spectrum_2dir(R, 0.1, 0.2)
+    ref = np.imag(0.1 * 0.2 * 12 * np.fft.ifft(np.fft.fft(R, axis=1), axis=0))
+    np.testing.assert_allclose(I, ref, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(w1, 2 * np.pi * np.arange(10) / (10 * 0.1))
+    np.testing.assert_allclose(w3, 2 * np.pi * np.arange(12) / (12 * 0.2))
