@@ -1,18 +1,26 @@
 """Benchmark of the CHFPE hot path on one MI355X.
 
-One step = the whole hot path once on the two-mode 32^4 depth-3 workload
-(10 hierarchy elements, 10,485,760 values per state, FP64):
+Default workload: three modes on a 24^6 (q, p) grid, depth 2 (10 hierarchy
+elements, 1,911,029,760 values per state, 15.3 GB in FP64), FP64 throughout.
+Its whole 2D THz-Raman job (4000 equilibration steps, then 64 t1 x 256 t2
+samples at stride 1) is 20383 RK4 steps, about half an hour on one GPU, so a
+bench step is a fixed slice of that job in which every stage of the path
+runs at the job's full grid and depth:
   coefficient tables and upload (chfpe_setup into a resident workspace),
-  equilibration (Boltzmann start + 4000 RK4 steps),
-  2D THz-Raman response R(t2, t1) over 64 t1 x 256 t2 samples (stride 1,
-  dt = 0.005), and the 2D spectrum of R.
-That is 4000 + 63 + 64 * 255 = 20383 RK4 steps per bench step.
+  Boltzmann start + 16 equilibration RK4 steps,
+  A^x excitation, then the t1 columns j1 = 0, 1 of R(t2, t1), each with its
+  B^x excitation and 8 t2 samples (7 RK4 steps apart, stride 1, dt = 0.005),
+  and the 2D spectrum of those columns.
+That is 16 + 1 + 2 * 7 = 31 RK4 steps per bench step; the whole job's time
+is reported as projected from the measured rate (--slice full runs it).
+The two-mode 32^4 workload (--workload two_mode_32) runs its whole job per
+step (20383 RK4 steps, 64 t1 branches in one FP64 wave).
 
 Prints one JSON line: hierarchy-gridpoint RK4 updates/s over the timed
 steps, the roofline of the dominant kernel (HIP-event timing of sampled RK4
 steps inside the timed region; algorithmic bytes per launch from the
-library), and the FP64 CPU oracle timed on a bounded sample of the same
-workload.
+library), the whole path against the 16-pass floor of classical RK4, and
+the FP64 CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -65,49 +73,107 @@ def rk4_steps(w) -> int:
             + int(w["n_t1"]) * (int(w["n_t2"]) - 1) * int(w["stride2"]))
 
 
+# Bench-step slices (equilibration steps, t1 columns, t2 samples) of jobs too
+# long to run whole per step; other workloads run their whole job.
+SLICES = {"three_mode_24": (16, 2, 8)}
+
+
+def job_slice(w, name: str, spec: str):
+    """(workload of one bench step, description).  spec: "" (default slice),
+    "full", or "EQ,N_T1,N_T2"."""
+    full = dict(w)
+    if spec == "full" or (not spec and name not in SLICES):
+        return full, "the whole job"
+    eq, n1, n2 = SLICES[name] if not spec else (int(x) for x in spec.split(","))
+    sl = dict(w, eq_steps=eq, n_t1=n1, n_t2=n2)
+    return sl, (f"a slice of the job: Boltzmann start + {eq} equilibration RK4 steps, A^x, t1 columns "
+                f"0..{n1 - 1}, each with B^x and {n2} t2 samples")
+
+
+def describe(name: str, w) -> str:
+    M = int(w["M"])
+    grid = "x".join(str(n) for n in list(w["Nq"]) + list(w["Np"]))
+    same = len(set(list(w["Nq"]) + list(w["Np"]))) == 1
+    if same:
+        grid = f"{w['Nq'][0]}^{2 * M}"
+    return (f"{name}: {M} mode{'s' if M > 1 else ''}, {grid} (q,p) grid, depth {w['K']}; "
+            f"job = equilibration {w['eq_steps']} + 2D THz-Raman {w['n_t1']} t1 x {w['n_t2']} t2 samples "
+            f"(stride {w['stride1']}, dt {w['dt']}) = {rk4_steps(w)} RK4 steps")
+
+
 def launches_per_rk4_step(M: int) -> dict:
-    d = {"pblock_rhs": 4, "qpass_rk4_s1": 1, "qpass_rk4_s2": 1, "qpass_rk4_s3": 1, "qpass_rk4_s4": 1}
+    d = {"pcube_rhs" if M == 3 else "pblock_rhs": 4, "qpass_rk4_s1": 1, "qpass_rk4_s2": 1,
+         "qpass_rk4_s3": 1, "qpass_rk4_s4": 1}
     if M == 3:
         d["qpass_acc"] = 4
     return d
 
 
-def cpu_baseline(w, pk, target_s: float, sample_note: str):
-    """Time the oracle's RK4 on this workload's state for ~target_s seconds
-    and compare the GPU's result for the same steps."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, solver, target_s: float):
+    """Time the FP64 CPU oracle on this workload's full state and compare the
+    GPU's result for the same work (relative L2).  States above 5e8 values:
+    one right-hand side (an RK4 step is four), else RK4 steps for about
+    target_s seconds."""
     import numpy as np
     import oracle as orc
     W0 = orc.boltzmann(w)
     W0[1] = 0.2 * W0[0]  # a non-stationary start so the steps do real work
-    t0 = time.perf_counter()
-    W1 = orc.rk4(w, W0, 1, w["dt"])
-    t1 = time.perf_counter() - t0
-    n = max(1, min(64, int(target_s / max(t1, 1e-3)) - 1))
-    t0 = time.perf_counter()
-    Wn = orc.rk4(w, W1, n, w["dt"])
-    tn = time.perf_counter() - t0
     S = W0.size
-    with pk.Solver(pk.params_from_workload(w)) as s:
-        s.set_state(W0)
-        s.propagate(n + 1, w["dt"])
-        got = s.get_state()
-    err = float(np.linalg.norm(got - Wn.ravel()) / np.linalg.norm(Wn.ravel()))
+    M = int(w["M"])
+    if S > 500_000_000:
+        t0 = time.perf_counter()
+        ref = orc.rhs(w, W0).ravel()
+        tn = time.perf_counter() - t0
+        solver.set_state(W0)
+        del W0
+        solver.rhs()
+        got = solver.get_state().ravel()
+        value = S / (4.0 * tn)
+        sample = (f"one oracle right-hand side of the full {M}-mode state ({S} values, {tn:.1f} s); "
+                  f"an RK4 step is four right-hand sides, so updates/s = values / (4 x that time)")
+        n_cmp = "1 right-hand side"
+    else:
+        t0 = time.perf_counter()
+        W1 = orc.rk4(w, W0, 1, w["dt"])
+        t1 = time.perf_counter() - t0
+        n = max(1, min(64, int(target_s / max(t1, 1e-3)) - 1))
+        t0 = time.perf_counter()
+        ref = orc.rk4(w, W1, n, w["dt"]).ravel()
+        tn = time.perf_counter() - t0
+        solver.set_state(W0)
+        solver.propagate(n + 1, w["dt"])
+        got = solver.get_state().ravel()
+        value = S * n / tn
+        sample = f"{n} FP64 oracle RK4 steps ({tn:.1f} s) of the full {M}-mode state ({S} values)"
+        n_cmp = f"{n + 1} RK4 steps"
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
     return {
-        "value": S * n / tn,
+        "value": value,
         "unit": "updates/s",
         "cores": orc.num_threads(),
         "kind": "oracle",
-        "sample": f"{n} FP64 RK4 steps ({tn:.1f} s) of the {w['M']}-mode state ({S} values) "
-                  f"{sample_note}",
-    }, err, n + 1
+        "sample": sample,
+        "cpu_model": cpu_model(),
+        "nproc": os.cpu_count(),
+    }, err, n_cmp
 
 
 
 # ---------------------------------------------------------------------------
 # rocprofv3 output -> text summaries under profiles/ (runs without a GPU)
 
-_EPI_KIND = {0: "qpass_acc", 1: "qpass_out", 2: "qpass_rk4_s1", 3: "qpass_rk4_s2",
-             4: "qpass_rk4_s3", 5: "qpass_rk4_s4"}
+# k_qpass epilogues; the two middle RK4 stages share one instantiation
+_EPI_KIND = {0: "qpass_acc", 1: "qpass_out", 2: "qpass_rk4_s1", 3: "qpass_rk4_s23", 4: "qpass_rk4_s4"}
 
 
 def _short_name(name: str) -> str:
@@ -123,6 +189,8 @@ def _kind_of(short: str, grid: int, min_grid: dict):
     targs = [a.strip() for a in short[short.find("<") + 1:short.rfind(">")].split(",")] if "<" in short else []
     if fam == "k_pblock":
         kind = "perturb" if targs[5] == "true" else "pblock_rhs"  # <T, TO, NMAX, RPT, MM, PERTURB, CLOS>
+    elif fam == "k_pcube":
+        kind = "perturb" if targs[4] == "true" else "pcube_rhs"  # <T, TO, NB1, SPLIT, PERTURB, CLOS>
     elif fam == "k_qpass":
         if int(targs[5]) == 2:        # dX/dq field: second launch of a perturbation
             kind = "perturb_q"
@@ -306,8 +374,10 @@ def summarise(args) -> int:
 
 def auto_batch(pk, w, prec, total_bytes: int) -> int:
     """Largest branch batch (at most n_t1) whose workspace fits in 85% of the
-    device memory."""
+    device memory; 1 for states of 2 GB or more, which fill the GPU alone."""
     n_t1 = int(w.get("n_t1", 1))
+    if pk.workspace_bytes(pk.params_from_workload(w, precision=pk.CHFPE_FP64, batch=1)) >= 6 * 2e9:
+        return 1
     base = pk.workspace_bytes(pk.params_from_workload(w, precision=pk.CHFPE_FP64, batch=1))
     one = pk.workspace_bytes(pk.params_from_workload(w, precision=prec, batch=1))
     two = pk.workspace_bytes(pk.params_from_workload(w, precision=prec, batch=2))
@@ -321,8 +391,11 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="two_mode_32")
-    ap.add_argument("--timing-every", type=int, default=64,
+    ap.add_argument("--workload", default="three_mode_24")
+    ap.add_argument("--slice", default="",
+                    help="bench step: 'full' (the whole job), 'EQ,N_T1,N_T2', or empty for the "
+                         "workload's default (three_mode_24: 16,2,8; others: the whole job)")
+    ap.add_argument("--timing-every", type=int, default=8,
                     help="bracket every k-th RK4 step's launches with HIP events")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--batch", type=int, default=0,
@@ -404,7 +477,8 @@ def main(argv=None):
     if args.mode == "bench" and w["kind"] != "2d":
         print(f"bench mode needs a 2D-response workload ({args.workload} is {w['kind']})", file=sys.stderr)
         return 2
-    steps_per = rk4_steps(w) if w["kind"] == "2d" else int(w["eq_steps"]) + int(w["n_t"]) - 1
+    ws, slice_desc = job_slice(w, args.workload, args.slice) if w["kind"] == "2d" else (w, "")
+    steps_per = rk4_steps(ws) if w["kind"] == "2d" else int(w["eq_steps"]) + int(w["n_t"]) - 1
     torch.cuda.init()
     prec = pk.CHFPE_FP32 if args.precision == "f32" else pk.CHFPE_FP64
     if args.mode == "rk4":
@@ -668,8 +742,8 @@ def main(argv=None):
         solver.rebuild()
         if timing_every:
             solver.set_kernel_timing(timing_every)
-        solver.equilibrate(int(w["eq_steps"]), dt)
-        R = solver.response_2d(w["A"], w["B"], w["C"], int(w["n_t1"]), int(w["n_t2"]),
+        solver.equilibrate(int(ws["eq_steps"]), dt)
+        R = solver.response_2d(w["A"], w["B"], w["C"], int(ws["n_t1"]), int(ws["n_t2"]),
                                int(w["stride1"]), int(w["stride2"]), dt)
         I = pk.spectrum_2d(R, int(w["stride1"]) * dt, int(w["stride2"]) * dt)
         return R, I
@@ -727,7 +801,7 @@ def main(argv=None):
                     "timed_launches": kt[dom][0]}
     # whole hot path against the 16-pass algorithmic floor of classical RK4
     tb = 4 if args.precision == "f32" else 8
-    n_branch = int(w["n_t1"]) * (int(w["n_t2"]) - 1) * int(w["stride2"])
+    n_branch = int(ws["n_t1"]) * (int(ws["n_t2"]) - 1) * int(w["stride2"])
     n_fp64 = steps_per - n_branch
     alg_bytes = 16.0 * S * (8 * n_fp64 + tb * n_branch) * args.steps
     step_alg = {"algorithmic_GBps": alg_bytes / total / 1e9,
@@ -737,8 +811,8 @@ def main(argv=None):
     parity = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
-        cpu, parity, nst = cpu_baseline(w, pk, args.cpu_seconds,
-                                        f"of the {steps_per} per bench step")
+        cpu, parity, parity_of = cpu_baseline(w, solver, args.cpu_seconds)
+        cpu["sample"] += f"; the GPU result of the same work: relative L2 {parity:.1e} ({parity_of})"
     solver.close()
 
     out = {
@@ -754,15 +828,17 @@ def main(argv=None):
         "vs_baseline": None,
         "dtype": args.precision,
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: 2 modes, 32^4 (q,p) grid, depth 3 (10 elements), "
-                               f"equilibration 4000 + 2D THz-Raman 64 t1 x 256 t2 RK4 steps, dt {dt}",
+        "config": {"workload": describe(args.workload, w) + f"; bench step = {slice_desc} "
+                               f"({steps_per} RK4 steps)",
                    "values_per_state": S, "rk4_steps_per_step": steps_per,
+                   "job_rk4_steps": rk4_steps(w),
+                   "job_seconds_projected": rk4_steps(w) * (ms_per_step / 1000.0) / steps_per,
                    "branch_batch": args.batch, "branch_precision": args.precision,
                    "tiles": tiles, "tiles_arg": tiles_arg},
         "roofline": roofline,
         "path_roofline_16pass": step_alg,
         "cpu_baseline": cpu,
-        "spectrum_time_s": ms_per_step / 1000.0,
+        "spectrum_time_s": rk4_steps(w) * (ms_per_step / 1000.0) / steps_per,
         "parity_rel_l2_vs_oracle": parity,
         "kernel_mean_ms": {k: v[1] for k, v in kt.items() if v[0] > 0},
     }

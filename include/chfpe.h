@@ -20,7 +20,12 @@
  *     differences; zero values outside the box) acts on the smooth factor
  *     h_n of W_n = exp(-beta H_sys/2) h_n, the factorization of Sec. III A,
  *     along every q and p axis; time integration is classical RK4 with a
- *     fixed step.  Device buffers hold h; the functions below exchange W.
+ *     fixed step.  The discrete hierarchy is linear with a time-independent
+ *     generator L, for which one classical RK4 step equals the degree-4
+ *     Taylor polynomial of dt L; the device evaluates that polynomial in
+ *     nested form, y <- y + dt L (y + dt/2 L (y + dt/3 L (y + dt/4 L y))),
+ *     equal to the stage-by-stage form up to rounding.  Device buffers hold
+ *     h; the functions below exchange W.
  *   - A context is not thread-safe; distinct contexts are independent.
  *   - All device work of a context runs on the stream given to chfpe_setup;
  *     functions that return host data synchronize that stream first.
@@ -63,7 +68,7 @@ enum { CHFPE_FP64 = 0, CHFPE_FP32 = 1 };
  *     every reduction stay FP64.  Everything else is FP64.
  *   batch: t1 branches propagated together by chfpe_response_2d (0 = 1);
  *     with batch > 1 or CHFPE_FP32, branches run in waves of `batch` states
- *     (batch x 5 extra state buffers of the branch type in the workspace),
+ *     (batch x 4 extra state buffers of the branch type in the workspace),
  *     each wave's t2 loop as one captured HIP graph.
  * Limits: 1 <= M <= 3, 0 <= K <= 12, 5 <= N <= 48 on every axis (the last
  * two p axes also within the tiling limit under chfpe_setup), all
@@ -103,7 +108,7 @@ typedef struct {
 typedef struct chfpe_ctx chfpe_ctx;
 
 /* Bytes of device workspace chfpe_setup needs for these parameters (tables,
- * seven FP64 state buffers, the batched branch buffers, reduction scratch),
+ * six FP64 state buffers, the batched branch buffers, reduction scratch),
  * or 0 if the parameters are invalid.  The caller may allocate it (e.g. as a torch tensor) and pass it
  * to chfpe_setup. */
 size_t chfpe_workspace_bytes(const chfpe_params *p);
@@ -173,6 +178,19 @@ int chfpe_response_2d_range(chfpe_ctx *ctx, const chfpe_optical *A, const chfpe_
                             const chfpe_optical *C, int64_t j1_begin, int64_t j1_end, int64_t n_t2,
                             int32_t stride1, int32_t stride2, double dt, double *R);
 
+/* Third-order response, Eq. (3Dresponse), at one waiting time
+ * t2 = t2_steps * dt, for the 2D IR spectrum of Sec. IV C:
+ *   R[j3 * n_t1 + j1] = integral D W_0 of
+ *       G(j3 * stride3 * dt) C^x G(t2) B^x G(j1 * stride1 * dt) A^x W_eq.
+ * R is a host array of n_t3 * n_t1 doubles (t1 fastest).  The t1 branches
+ * run one after another on the FP64 single-state buffers whatever the
+ * context's batch and precision.  Uses W_eq (ESTATE before equilibration);
+ * overwrites the current state.  EINVAL for negative counts or strides, a
+ * zero stride with more than one sample, or dt <= 0 with steps to take. */
+int chfpe_response_3d(chfpe_ctx *ctx, const chfpe_optical *A, const chfpe_optical *B, const chfpe_optical *C,
+                      const chfpe_optical *D, int64_t n_t1, int64_t t2_steps, int64_t n_t3, int32_t stride1,
+                      int32_t stride3, double dt, double *R);
+
 /* Number of values in a state: |{n : |n| <= K}| * prod_s Nq_s * Np_s. */
 int64_t chfpe_state_count(const chfpe_ctx *ctx);
 
@@ -208,6 +226,13 @@ int chfpe_spectrum_1d(const double *R, int64_t n, double tau, double *omega, dou
                       void *hip_stream);
 int chfpe_spectrum_2d(const double *R, int64_t n_t1, int64_t n_t2, double tau1, double tau2,
                       double *I, void *hip_stream);
+/* 2D IR spectrum of a third-order response, Eq. (noncorrelation), at its
+ * waiting time: R and I are [n_t3][n_t1] (t1 fastest) and
+ *   I[k3 * n_t1 + k1] = Im{ tau1 tau3 sum_{j1,j3}
+ *           exp(-i omega1_k1 t1_j1 + i omega3_k3 t3_j3) R[j3 * n_t1 + j1] },
+ * same conventions, scratch and errors as chfpe_spectrum_2d. */
+int chfpe_spectrum_2dir(const double *R, int64_t n_t1, int64_t n_t3, double tau1, double tau3,
+                        double *I, void *hip_stream);
 
 /* Bandwidth reference: copy `bytes` bytes (a multiple of 16) from src to
  * dst, both device pointers, with a plain streaming kernel on hip_stream. */

@@ -15,7 +15,7 @@ import os
 import numpy as np
 
 __all__ = ["Params", "Optical", "Solver", "ChfpeError", "lib", "params_from_workload",
-           "optical_from_dict", "workspace_bytes", "stream_copy", "spectrum_1d", "spectrum_2d",
+           "optical_from_dict", "workspace_bytes", "stream_copy", "spectrum_1d", "spectrum_2d", "spectrum_2dir",
            "closure_rows", "closure_features", "closure_eval", "closure_grad", "ClosureTrainer",
            "CLOSURE_PARAMS", "LIB_PATH"]
 
@@ -85,6 +85,8 @@ def lib():
     L.chfpe_response_2d.restype = ctypes.c_int
     L.chfpe_response_2d_range.argtypes = [vp, O, O, O, i64, i64, i64, i32, i32, ctypes.c_double, dp]
     L.chfpe_response_2d_range.restype = ctypes.c_int
+    L.chfpe_response_3d.argtypes = [vp, O, O, O, O, i64, i64, i64, i32, i32, ctypes.c_double, dp]
+    L.chfpe_response_3d.restype = ctypes.c_int
     L.chfpe_state_count.argtypes = [vp]
     L.chfpe_state_count.restype = i64
     L.chfpe_get_state.argtypes = [vp, dp]
@@ -103,6 +105,8 @@ def lib():
     L.chfpe_spectrum_1d.restype = ctypes.c_int
     L.chfpe_spectrum_2d.argtypes = [dp, i64, i64, ctypes.c_double, ctypes.c_double, dp, vp]
     L.chfpe_spectrum_2d.restype = ctypes.c_int
+    L.chfpe_spectrum_2dir.argtypes = [dp, i64, i64, ctypes.c_double, ctypes.c_double, dp, vp]
+    L.chfpe_spectrum_2dir.restype = ctypes.c_int
     L.chfpe_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
     L.chfpe_stream_copy.restype = ctypes.c_int
     L.chfpe_set_kernel_timing.argtypes = [vp, i32]
@@ -300,6 +304,17 @@ def spectrum_2d(R, tau1: float, tau2: float, stream=None):
     return I
 
 
+def spectrum_2dir(R, tau1: float, tau3: float, stream=None):
+    """I(omega3, t2, omega1) of Eq. (noncorrelation) on the device; R has shape (n_t3, n_t1)."""
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    n3, n1 = R.shape
+    I = np.empty_like(R)
+    rc = lib().chfpe_spectrum_2dir(_dptr(R), n1, n3, float(tau1), float(tau3), _dptr(I), _stream_handle(stream))
+    if rc != 0:
+        raise ChfpeError(rc, "spectrum_2dir failed")
+    return I
+
+
 class Solver:
     """One solver context: workspace allocated by torch on ``device``,
     work issued on the current torch stream of that device."""
@@ -396,6 +411,15 @@ class Solver:
         self._check(lib().chfpe_response_2d_range(self._ctx, ctypes.byref(oa), ctypes.byref(ob), ctypes.byref(oc),
                                                   int(j1_begin), int(j1_end), int(n_t2), int(stride1),
                                                   int(stride2), float(dt), _dptr(R)))
+        return R
+
+    def response_3d(self, A: dict, B: dict, C: dict, D: dict, n_t1: int, t2_steps: int, n_t3: int,
+                    stride1: int, stride3: int, dt: float) -> np.ndarray:
+        """R^(3)[j3, j1] of Eq. (3Dresponse) at t2 = t2_steps * dt; shape (n_t3, n_t1)."""
+        R = np.empty((int(n_t3), int(n_t1)))
+        ops = [optical_from_dict(X) for X in (A, B, C, D)]
+        self._check(lib().chfpe_response_3d(self._ctx, *[ctypes.byref(o) for o in ops], int(n_t1), int(t2_steps),
+                                            int(n_t3), int(stride1), int(stride3), float(dt), _dptr(R)))
         return R
 
     def get_state(self) -> np.ndarray:

@@ -5,11 +5,13 @@
 // exp(-beta U(q)/2) exp(-sum_s beta p_s^2/4m_s).
 // A context owns (inside one device workspace) the coefficient tables of the
 // right-hand side of Eq. (eq:HEOM), the equilibrium W_eq, the t1-branch state
-// U of the double loop of Sec. IV C, and the buffers of classical RK4:
-// y (the propagated state), yacc (running sum of the RK4 combination), xa/xb
-// (stage inputs, alternating) and t (partial right-hand side).  One RK4 step
-// is four stages; a stage is one k_pblock launch followed by one (M <= 2) or
-// two (M = 3) k_qpass launches, the last of which applies the stage update.
+// U of the double loop of Sec. IV C, and the buffers of RK4: y (the
+// propagated state), xa/xb (stage states, alternating) and t (partial
+// right-hand side).  One RK4 step is the degree-4 Taylor polynomial of the
+// generator, which classical RK4 equals for a linear time-independent
+// system, in nested form (four stages, see Epi in kernels.h).  A stage is one
+// p-axis launch (k_pblock, or k_pcube for three modes) followed by one or two
+// k_qpass launches, the last of which applies the stage update.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,7 +43,7 @@ constexpr int kQThreadsMax = 512;    // largest k_qpass workgroup
 
 // Kernel kinds for event timing; batched launches (several branch states per
 // launch) are kept apart from single-state ones.
-constexpr int kNumBase = 9;
+constexpr int kNumBase = 10;
 constexpr int kNumKinds = 2 * kNumBase;
 enum Kind : int {
   K_PBLOCK = 0,
@@ -52,14 +54,18 @@ enum Kind : int {
   K_QS4 = 5,
   K_OBSERVE = 6,
   K_PERTURB = 7,
-  K_QOUT = 8
+  K_QOUT = 8,
+  K_PCUBE = 9
 };
 const char *kKindNames[kNumKinds] = {
     "pblock_rhs", "qpass_acc", "qpass_rk4_s1", "qpass_rk4_s2", "qpass_rk4_s3", "qpass_rk4_s4", "observe",
-    "perturb", "qpass_out", "batch_pblock_rhs", "batch_qpass_acc", "batch_qpass_rk4_s1", "batch_qpass_rk4_s2",
-    "batch_qpass_rk4_s3", "batch_qpass_rk4_s4", "batch_observe", "batch_perturb", "batch_qpass_out"};
-// state passes each kind reads plus writes (each input once, each output once)
-const double kKindPasses[kNumBase] = {2, 3, 4, 6, 6, 4, 0.1, 2, 3};
+    "perturb", "qpass_out", "pcube_rhs", "batch_pblock_rhs", "batch_qpass_acc", "batch_qpass_rk4_s1",
+    "batch_qpass_rk4_s2", "batch_qpass_rk4_s3", "batch_qpass_rk4_s4", "batch_observe", "batch_perturb",
+    "batch_qpass_out", "batch_pcube_rhs"};
+// state passes each kind reads plus writes (each input once, each output
+// once): the first stage reads its input (y) and t and writes z1; later
+// stages also read y (the last one reads and writes it in place)
+const double kKindPasses[kNumBase] = {2, 3, 3, 4, 4, 4, 0.1, 2, 3, 2};
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -215,11 +221,14 @@ bool derive(const chfpe_params *p, Derived &d, std::string &err) {
   return true;
 }
 
+constexpr int kStateBufs = 6;   // FP64: W_eq, U, y, xa, xb, t
+constexpr int kBranchBufs = 4;  // per branch of a wave: y, xa, xb, t
+
 // Workspace layout (byte offsets, 256-aligned).
 struct Layout {
-  size_t F, VpQ, Vp, pm, pg, gA, gB, Cw, wp, sq, sp, up, dn, cc, tc, damp, partial, scal, flag, clos;
-  size_t bufs[7];
-  size_t bbufs[5];  // batched branch buffers: y, yacc, xa, xb, t (B states each)
+  size_t F, VpQ, Vp, pm, pg, gA, gB, gC, Cw, wp, sq, sp, up, dn, cc, tc, damp, partial, scal, flag, clos;
+  size_t bufs[kStateBufs];
+  size_t bbufs[kBranchBufs];  // batched branch buffers: y, xa, xb, t (B states each)
   size_t total;
 };
 constexpr int kPartials = 2048;
@@ -239,6 +248,7 @@ Layout layout(const Derived &d) {
   L.pg = take(sizeof(double) * 3 * kTab);
   L.gA = take(sizeof(double) * 3 * d.Q);
   L.gB = take(sizeof(double) * 3 * d.Q);
+  L.gC = take(sizeof(double) * 3 * d.Q);
   L.Cw = take(sizeof(double) * d.Q);
   L.wp = take(sizeof(double) * d.P);
   L.sq = take(sizeof(double) * d.Q);
@@ -252,9 +262,9 @@ Layout layout(const Derived &d) {
   L.scal = take(sizeof(double) * 16);
   L.flag = take(sizeof(int) * 16);
   L.clos = take(sizeof(double) * 6 * 2 * kClosRows * kTab);  // closure weights [axis][orientation][6][kTab]
-  for (int i = 0; i < 7; ++i) L.bufs[i] = take(sizeof(double) * (size_t)d.S);
+  for (int i = 0; i < kStateBufs; ++i) L.bufs[i] = take(sizeof(double) * (size_t)d.S);
   const size_t tsz = d.prec == CHFPE_FP32 ? sizeof(float) : sizeof(double);
-  for (int i = 0; i < 5; ++i) L.bbufs[i] = d.batched ? take(tsz * (size_t)d.S * d.B) : 0;
+  for (int i = 0; i < kBranchBufs; ++i) L.bbufs[i] = d.batched ? take(tsz * (size_t)d.S * d.B) : 0;
   L.total = o;
   return L;
 }
@@ -269,6 +279,12 @@ struct Launch {
   // three modes.
   QPass qa{}, qf{}, qx{};
   bool has_qa = false, qf_two = false, has_qx = false;
+  // three modes: all p axes of a q point in one k_pcube task (then the q
+  // passes are (q_2, q_3) and q_1 alone, and excitations need no qx)
+  bool pcube = false, pcube_split = false;
+  PCube pcb{};
+  int pcube_threads = 0, pcube_nb1 = 0;
+  size_t pcube_lds = 0;
   int qa_threads = 0, qf_threads = 0, qx_threads = 0;
   size_t qa_lds = 0, qf_lds = 0;
   int qa_nmax = 48, qf_nmax = 48, qx_nmax = 48;
@@ -309,10 +325,10 @@ struct chfpe_ctx {
   hipStream_t stream = nullptr;
   unsigned char *ws = nullptr;
   bool own_ws = false;
-  double *F, *VpQ, *Vp, *pm, *pg, *gA, *gB, *Cw, *wp, *sq, *sp, *cc, *tc, *damp, *partial, *scal;
+  double *F, *VpQ, *Vp, *pm, *pg, *gA, *gB, *gC, *Cw, *wp, *sq, *sp, *cc, *tc, *damp, *partial, *scal;
   int *up, *dn, *flag;
-  double *weq, *u, *y, *yacc, *xa, *xb, *t;
-  void *bb[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // batched y, yacc, xa, xb, t
+  double *weq, *u, *y, *xa, *xb, *t;
+  void *bb[kBranchBufs] = {nullptr, nullptr, nullptr, nullptr};  // batched y, xa, xb, t
   // cached graph of one wave's t2 loop
   hipGraphExec_t wave_graph = nullptr;
   long long wave_key[6] = {0, 0, 0, 0, 0, 0};
@@ -331,6 +347,7 @@ struct chfpe_ctx {
   bool capturing = false;  // a HIP graph is being captured: no event timing
   bool closure_on = false; // right-hand sides use the closure stencil weights (tb.clos)
   bool use_graphs = true;
+  bool allow_pcube = true;  // three modes: k_pcube where the p block fits it
   // kernel timing
   int timing_every = 0;
   long long step_counter = 0;
@@ -568,6 +585,25 @@ void plan_one(chfpe_ctx *c, int a, int run, std::vector<int> rest, QPass &out, i
   nmax = nmax_bucket(axis_len(c->d, a));
 }
 
+// LDS of a k_pcube workgroup: two fields of one round's (p_2, p_3) planes,
+// one pad value per p_3 row.
+size_t pcube_lds_bytes(const Derived &d, size_t tsize) {
+  const int pl = pcube_planes(nmax_bucket(d.Np[0]));
+  return 2 * (size_t)pl * d.Np[1] * (d.Np[2] + 1) * tsize;
+}
+
+// Three modes take k_pcube when its register lines (p_1, at most 32 points)
+// and its (p_2, p_3) plane of threads fit one workgroup (FP64 bound).
+bool pcube_fits(const chfpe_ctx *c) {
+  const Derived &d = c->d;
+  if (d.M != 3 || !c->allow_pcube) return false;
+  const int nb1 = nmax_bucket(d.Np[0]);
+  const int plane = d.Np[1] * d.Np[2];
+  const int maxthr = nb1 >= 32 ? pcube_max_threads<double, 32>() : nb1 >= 24 ? pcube_max_threads<double, 24>()
+                                                                            : pcube_max_threads<double, 16>();
+  return nb1 <= 32 && (plane + 63) / 64 * 64 <= maxthr && pcube_lds_bytes(d, sizeof(double)) <= 160 * 1024;
+}
+
 // Choose tile shapes.  Returns false when a k_qpass launch over every state
 // of the largest batch would exceed one dispatch (the k_pblock shape always
 // fits: derive() checked it).
@@ -622,6 +658,30 @@ bool plan(chfpe_ctx *c) {
     ln.qf_two = true;
     plan_two(c, 0, 1, d.P, {}, ln.qf, ln.qf_threads, ln.qf_lds, ln.qf_nmax);
     ln.has_qx = false;
+  } else if (pcube_fits(c)) {
+    // all p axes per q point (k_pcube), then (q_2, q_3) over whole p-blocks,
+    // then q_1 alone (lines in registers) with the stage update
+    ln.pcube = true;
+    PCube &pq = ln.pcb;
+    pq.N1 = d.Np[0];
+    pq.N2 = d.Np[1];
+    pq.N3 = d.Np[2];
+    pq.plane = pq.N2 * pq.N3;
+    pq.ntasks = (int)std::min<long long>((long long)d.ne * d.Q, 1LL << 30);
+    pq.nblk = pad8(pq.ntasks);
+    ln.pcube_nb1 = nmax_bucket(pq.N1);
+    ln.pcube_threads = (pq.plane + 63) / 64 * 64;
+    ln.pcube_lds = pcube_lds_bytes(d, sizeof(double));
+    ln.pcube_split = pq.N1 == ln.pcube_nb1 && pq.N2 == pq.N1 && pq.N3 == pq.N1 && c->tune_pb_split != 0;
+    pb.nb = 1;  // k_pblock is not launched: one shape for the autotuner
+    pb.split = ln.pcube_split ? 1 : 0;
+    pb.run = 1;
+    ln.has_qa = true;
+    plan_two(c, 1, 2, d.P, {0}, ln.qa, ln.qa_threads, ln.qa_lds, ln.qa_nmax);
+    ln.qf_two = false;
+    plan_one(c, 0, (d.Q / d.Nq[0]) * d.P, {}, ln.qf, ln.qf_threads, ln.qf_nmax);
+    ln.qf_lds = 0;
+    ln.has_qx = false;
   } else {
     // (q_2, q_3) over whole p-blocks, then (q_1, p_1) over (p_2, p_3) planes
     const int plane = d.Np[1] * d.Np[2];
@@ -634,7 +694,8 @@ bool plan(chfpe_ctx *c) {
   }
   auto fits = [&](const QPass &q, int thr) { return grid_items((long long)q.ntasks * nbat, thr) <= kMaxGridItems; };
   return fits(ln.qf, ln.qf_threads) && (!ln.has_qa || fits(ln.qa, ln.qa_threads)) &&
-         (!ln.has_qx || fits(ln.qx, ln.qx_threads));
+         (!ln.has_qx || fits(ln.qx, ln.qx_threads)) &&
+         (!ln.pcube || grid_items((long long)ln.pcb.ntasks * nbat, ln.pcube_threads) <= kMaxGridItems);
 }
 
 // --------------------------------------------------------------------------
@@ -709,6 +770,7 @@ void allow_lds(K kern, size_t bytes) {
 struct Batch {
   Geom g;
   PBlock pb;
+  PCube pcb;
   QPass qa, qf, qx;
 };
 
@@ -719,6 +781,9 @@ Batch batch_of(const chfpe_ctx *c, int nb) {
   b.pb = c->ln.pb;
   b.pb.ntasks *= nb;
   b.pb.nblk = pad8(b.pb.ntasks);
+  b.pcb = c->ln.pcb;
+  b.pcb.ntasks *= nb;
+  b.pcb.nblk = pad8(b.pcb.ntasks);
   QPass *q[3] = {&b.qa, &b.qf, &b.qx};
   const QPass *s[3] = {&c->ln.qa, &c->ln.qf, &c->ln.qx};
   for (int i = 0; i < 3; ++i) {
@@ -784,28 +849,66 @@ void launch_pblock_t(chfpe_ctx *c, const Batch &b, const T *X, TO *out, const do
   }
 }
 
+template <typename T, typename TO, int NB1, bool SPLIT, bool PERTURB>
+void launch_pcube_s(chfpe_ctx *c, const Batch &b, const T *X, TO *out, const double *grad) {
+  const Launch &ln = c->ln;
+  const size_t lds = pcube_lds_bytes(c->d, sizeof(T));
+  if constexpr (kClosureBuilt<T, TO, NB1>) {
+    if (c->closure_on) {
+      auto kern = k_pcube<T, TO, NB1, SPLIT, PERTURB, true>;
+      allow_lds(kern, lds);
+      hipLaunchKernelGGL(kern, dim3(b.pcb.nblk), dim3(ln.pcube_threads), lds, c->stream, b.g, c->tb, b.pcb, X,
+                         out, grad);
+      return;
+    }
+  }
+  auto kern = k_pcube<T, TO, NB1, SPLIT, PERTURB>;
+  allow_lds(kern, lds);
+  hipLaunchKernelGGL(kern, dim3(b.pcb.nblk), dim3(ln.pcube_threads), lds, c->stream, b.g, c->tb, b.pcb, X, out,
+                     grad);
+}
+
+template <typename T, typename TO, int NB1, bool PERTURB>
+void launch_pcube_n(chfpe_ctx *c, const Batch &b, const T *X, TO *out, const double *grad) {
+  if (c->ln.pcube_split)
+    launch_pcube_s<T, TO, NB1, true, PERTURB>(c, b, X, out, grad);
+  else
+    launch_pcube_s<T, TO, NB1, false, PERTURB>(c, b, X, out, grad);
+}
+
+template <typename T, typename TO, bool PERTURB>
+void launch_pcube_t(chfpe_ctx *c, const Batch &b, const T *X, TO *out, const double *grad) {
+  switch (c->ln.pcube_nb1) {
+    case 8: launch_pcube_n<T, TO, 8, PERTURB>(c, b, X, out, grad); break;
+    case 12: launch_pcube_n<T, TO, 12, PERTURB>(c, b, X, out, grad); break;
+    case 16: launch_pcube_n<T, TO, 16, PERTURB>(c, b, X, out, grad); break;
+    case 24: launch_pcube_n<T, TO, 24, PERTURB>(c, b, X, out, grad); break;
+    default: launch_pcube_n<T, TO, 32, PERTURB>(c, b, X, out, grad); break;
+  }
+}
+
 template <typename T, typename TO, int NMAX, bool TWO, int EPI, int FA, int FB>
 void launch_q_n(chfpe_ctx *c, const Batch &b, const QPass &qp, int threads, size_t lds, const T *X, TO *Tacc,
-                const TO *y, TO *yacc, TO *xo, const double *grad, double dt) {
+                const TO *y, TO *xo, const double *grad, double cst) {
   if constexpr (kClosureBuilt<T, TO, NMAX>) {
     if (c->closure_on) {
       auto kern = k_qpass<T, TO, NMAX, TWO, EPI, FA, FB, true>;
       allow_lds(kern, lds);
-      hipLaunchKernelGGL(kern, dim3(qp.nblk), dim3(threads), lds, c->stream, b.g, c->tb, qp, X, Tacc, y, yacc,
-                         xo, grad, dt);
+      hipLaunchKernelGGL(kern, dim3(qp.nblk), dim3(threads), lds, c->stream, b.g, c->tb, qp, X, Tacc, y, xo,
+                         grad, cst);
       return;
     }
   }
   auto kern = k_qpass<T, TO, NMAX, TWO, EPI, FA, FB>;
   allow_lds(kern, lds);
-  hipLaunchKernelGGL(kern, dim3(qp.nblk), dim3(threads), lds, c->stream, b.g, c->tb, qp, X, Tacc, y, yacc,
-                     xo, grad, dt);
+  hipLaunchKernelGGL(kern, dim3(qp.nblk), dim3(threads), lds, c->stream, b.g, c->tb, qp, X, Tacc, y, xo, grad,
+                     cst);
 }
 
 template <typename T, typename TO, bool TWO, int EPI, int FA, int FB>
 void launch_q_t(chfpe_ctx *c, const Batch &b, const QPass &qp, int threads, size_t lds, int nmax, const T *X,
-                TO *Tacc, const TO *y, TO *yacc, TO *xo, const double *grad, double dt) {
-#define CHFPE_QN(N) launch_q_n<T, TO, N, TWO, EPI, FA, FB>(c, b, qp, threads, lds, X, Tacc, y, yacc, xo, grad, dt)
+                TO *Tacc, const TO *y, TO *xo, const double *grad, double cst) {
+#define CHFPE_QN(N) launch_q_n<T, TO, N, TWO, EPI, FA, FB>(c, b, qp, threads, lds, X, Tacc, y, xo, grad, cst)
   switch (nmax) {
     case 8: CHFPE_QN(8); break;
     case 12: CHFPE_QN(12); break;
@@ -818,30 +921,32 @@ void launch_q_t(chfpe_ctx *c, const Batch &b, const QPass &qp, int threads, size
 }
 
 // One right-hand-side evaluation of X (t: partial right-hand side) fused with
-// the stage update EPI; all buffers hold b.g.nbatch states.
+// the stage epilogue EPI (coefficient cst); all buffers hold b.g.nbatch
+// states.  kind: the timing kind of the stage-final launch.
 template <typename T, int EPI>
-void launch_stage(chfpe_ctx *c, const Batch &b, const T *X, T *t, const T *y, T *yacc, T *xo, double dt) {
+void launch_stage(chfpe_ctx *c, const Batch &b, const T *X, T *t, const T *y, T *xo, double cst, int kind) {
   const Launch &ln = c->ln;
-  {
+  if (ln.pcube) {
+    TimedScope ts(c, K_PCUBE, b.g.nbatch, sizeof(T));
+    launch_pcube_t<T, T, false>(c, b, X, t, nullptr);
+  } else {
     TimedScope ts(c, K_PBLOCK, b.g.nbatch, sizeof(T));
     launch_pblock_t<T, T, false>(c, b, X, t, nullptr);
   }
   if (ln.has_qa) {
     TimedScope ts(c, K_QACC, b.g.nbatch, sizeof(T));
     launch_q_t<T, T, true, EPI_ACC, FQ, FQ>(c, b, b.qa, ln.qa_threads, ln.qa_lds, ln.qa_nmax, X, t, nullptr,
-                                            nullptr, nullptr, nullptr, dt);
+                                            nullptr, nullptr, 0.0);
   }
-  const int kind = EPI == EPI_S1 ? K_QS1 : EPI == EPI_S2 ? K_QS2 : EPI == EPI_S3 ? K_QS3
-                 : EPI == EPI_S4 ? K_QS4 : K_QOUT;
   TimedScope ts(c, kind, b.g.nbatch, sizeof(T));
-  if (c->d.M == 1)
-    launch_q_t<T, T, false, EPI, FQ, FQ>(c, b, b.qf, ln.qf_threads, 0, ln.qf_nmax, X, t, y, yacc, xo, nullptr, dt);
+  if (!ln.qf_two)  // one mode, or q_1 after k_pcube
+    launch_q_t<T, T, false, EPI, FQ, FQ>(c, b, b.qf, ln.qf_threads, 0, ln.qf_nmax, X, t, y, xo, nullptr, cst);
   else if (c->d.M == 2)
-    launch_q_t<T, T, true, EPI, FQ, FQ>(c, b, b.qf, ln.qf_threads, ln.qf_lds, ln.qf_nmax, X, t, y, yacc, xo,
-                                        nullptr, dt);
+    launch_q_t<T, T, true, EPI, FQ, FQ>(c, b, b.qf, ln.qf_threads, ln.qf_lds, ln.qf_nmax, X, t, y, xo, nullptr,
+                                        cst);
   else
-    launch_q_t<T, T, true, EPI, FQ, FP>(c, b, b.qf, ln.qf_threads, ln.qf_lds, ln.qf_nmax, X, t, y, yacc, xo,
-                                        nullptr, dt);
+    launch_q_t<T, T, true, EPI, FQ, FP>(c, b, b.qf, ln.qf_threads, ln.qf_lds, ln.qf_nmax, X, t, y, xo, nullptr,
+                                        cst);
 }
 
 // out = X^x W for every element of one state, arithmetic in FP64
@@ -850,10 +955,14 @@ template <typename TO>
 void launch_perturb(chfpe_ctx *c, const double *W, TO *out, const double *grad) {
   TimedScope ts(c, K_PERTURB);
   const Batch b = batch_of(c, 1);
+  if (c->ln.pcube) {
+    launch_pcube_t<double, TO, true>(c, b, W, out, grad);
+    return;
+  }
   launch_pblock_t<double, TO, true>(c, b, W, out, grad);
   if (c->ln.has_qx)
     launch_q_t<double, TO, false, EPI_ACC, FX, FQ>(c, b, b.qx, c->ln.qx_threads, 0, c->ln.qx_nmax, W, out,
-                                                   nullptr, nullptr, nullptr, grad, 0.0);
+                                                   nullptr, nullptr, grad, 0.0);
 }
 
 int last_launch_error(chfpe_ctx *c) {
@@ -862,27 +971,28 @@ int last_launch_error(chfpe_ctx *c) {
   return CHFPE_OK;
 }
 
-// The buffers of one classical RK4 integration: y (in place), yacc, the
-// alternating stage inputs xa/xb, and the partial right-hand side t.
+// The buffers of one RK4 integration: y (in place), the alternating stage
+// states xa/xb, and the partial right-hand side t.
 template <typename T>
 struct RK4Bufs {
-  T *y, *yacc, *xa, *xb, *t;
+  T *y, *xa, *xb, *t;
 };
 
-// n classical RK4 steps on b.g.nbatch states (in place).
+// n RK4 steps on b.g.nbatch states (in place), each the degree-4 Taylor
+// polynomial of dt L in nested form (see Epi in kernels.h).
 template <typename T>
 int rk4(chfpe_ctx *c, const Batch &b, const RK4Bufs<T> &r, long long nsteps, double dt) {
   for (long long st = 0; st < nsteps; ++st) {
     c->timing_now = c->timing_every > 0 && (c->step_counter % c->timing_every) == 0;
     ++c->step_counter;
-    // stage 1: k1 = f(y); yacc = y + dt/6 k1; xa = y + dt/2 k1
-    launch_stage<T, EPI_S1>(c, b, r.y, r.t, r.y, r.yacc, r.xa, dt);
-    // stage 2: k2 = f(xa); yacc += dt/3 k2; xb = y + dt/2 k2
-    launch_stage<T, EPI_S2>(c, b, r.xa, r.t, r.y, r.yacc, r.xb, dt);
-    // stage 3: k3 = f(xb); yacc += dt/3 k3; xa = y + dt k3
-    launch_stage<T, EPI_S3>(c, b, r.xb, r.t, r.y, r.yacc, r.xa, dt);
-    // stage 4: k4 = f(xa); y = yacc + dt/6 k4
-    launch_stage<T, EPI_S4>(c, b, r.xa, r.t, nullptr, r.yacc, r.y, dt);
+    // xa = y + dt/4 L y
+    launch_stage<T, EPI_H1>(c, b, r.y, r.t, nullptr, r.xa, 0.25 * dt, K_QS1);
+    // xb = y + dt/3 L xa
+    launch_stage<T, EPI_H2>(c, b, r.xa, r.t, r.y, r.xb, dt / 3.0, K_QS2);
+    // xa = y + dt/2 L xb
+    launch_stage<T, EPI_H2>(c, b, r.xb, r.t, r.y, r.xa, 0.5 * dt, K_QS3);
+    // y = y + dt L xa
+    launch_stage<T, EPI_H4>(c, b, r.xa, r.t, nullptr, r.y, dt, K_QS4);
     if (c->timing_now) {
       c->timing_now = false;
       if (c->pending.size() > 4096) {
@@ -897,7 +1007,7 @@ int rk4(chfpe_ctx *c, const Batch &b, const RK4Bufs<T> &r, long long nsteps, dou
 // FP64 single-state integration on buffer yb
 int rk4(chfpe_ctx *c, double *yb, long long nsteps, double dt) {
   const Batch b = batch_of(c, 1);
-  return rk4<double>(c, b, RK4Bufs<double>{yb, c->yacc, c->xa, c->xb, c->t}, nsteps, dt);
+  return rk4<double>(c, b, RK4Bufs<double>{yb, c->xa, c->xb, c->t}, nsteps, dt);
 }
 
 // dst[b * dstride] = <C>(state b of W), b < nb (Cw holds the C table)
@@ -920,7 +1030,7 @@ int observe_to(chfpe_ctx *c, const double *W, double *dst) {
 template <typename T>
 int enqueue_wave(chfpe_ctx *c, int nb, long long n_t2, int s2, double dt, double *Rw) {
   const Batch b = batch_of(c, nb);
-  const RK4Bufs<T> r{(T *)c->bb[0], (T *)c->bb[1], (T *)c->bb[2], (T *)c->bb[3], (T *)c->bb[4]};
+  const RK4Bufs<T> r{(T *)c->bb[0], (T *)c->bb[1], (T *)c->bb[2], (T *)c->bb[3]};
   for (long long j2 = 0; j2 < n_t2; ++j2) {
     if (j2 > 0) {
       int rc = rk4<T>(c, b, r, s2, dt);
@@ -1063,7 +1173,7 @@ int check_finite(chfpe_ctx *c, const double *W) {
 template <typename T>
 double time_batched(chfpe_ctx *c, int n_steps, double dt) {
   const Batch b = batch_of(c, c->d.B);
-  const RK4Bufs<T> r{(T *)c->bb[0], (T *)c->bb[1], (T *)c->bb[2], (T *)c->bb[3], (T *)c->bb[4]};
+  const RK4Bufs<T> r{(T *)c->bb[0], (T *)c->bb[1], (T *)c->bb[2], (T *)c->bb[3]};
   if (rk4<T>(c, b, r, 1, dt)) return -1.0;
   hipEvent_t e0 = get_event(c), e1 = get_event(c);
   if (!e0 || !e1) return -1.0;
@@ -1262,6 +1372,7 @@ int chfpe_setup(const chfpe_params *p, void *dev_workspace, size_t ws_bytes, voi
   c->pg = (double *)at(L.pg);
   c->gA = (double *)at(L.gA);
   c->gB = (double *)at(L.gB);
+  c->gC = (double *)at(L.gC);
   c->Cw = (double *)at(L.Cw);
   c->wp = (double *)at(L.wp);
   c->sq = (double *)at(L.sq);
@@ -1274,10 +1385,10 @@ int chfpe_setup(const chfpe_params *p, void *dev_workspace, size_t ws_bytes, voi
   c->partial = (double *)at(L.partial);
   c->scal = (double *)at(L.scal);
   c->flag = (int *)at(L.flag);
-  double **bp[7] = {&c->weq, &c->u, &c->y, &c->yacc, &c->xa, &c->xb, &c->t};
-  for (int i = 0; i < 7; ++i) *bp[i] = (double *)at(L.bufs[i]);
+  double **bp[kStateBufs] = {&c->weq, &c->u, &c->y, &c->xa, &c->xb, &c->t};
+  for (int i = 0; i < kStateBufs; ++i) *bp[i] = (double *)at(L.bufs[i]);
   if (d.batched)
-    for (int i = 0; i < 5; ++i) c->bb[i] = at(L.bbufs[i]);
+    for (int i = 0; i < kBranchBufs; ++i) c->bb[i] = at(L.bbufs[i]);
 
   make_geom(c);
   {
@@ -1295,6 +1406,7 @@ int chfpe_setup(const chfpe_params *p, void *dev_workspace, size_t ws_bytes, voi
   if (const char *v = std::getenv("CHFPE_TUNE_PB_SPLIT")) c->tune_pb_split = std::atoi(v);
   if (const char *v = std::getenv("CHFPE_TUNE_PB_RUN")) c->tune_pb_run = std::atoi(v);
   if (const char *v = std::getenv("CHFPE_NO_GRAPH")) c->use_graphs = std::atoi(v) == 0;
+  if (const char *v = std::getenv("CHFPE_PCUBE")) c->allow_pcube = std::atoi(v) != 0;
   std::vector<double> F, Vp, pm, pg, sq, sp, wp, cc, tc, damp;
   std::vector<int> up, dn;
   build_tables(c, F, Vp, pm, pg, sq, sp, wp, up, dn, cc, tc, damp);
@@ -1407,7 +1519,7 @@ int chfpe_propagate(chfpe_ctx *c, int64_t n_steps, double dt) {
 int chfpe_rhs(chfpe_ctx *c) {
   if (!c) return CHFPE_EINVAL;
   const Batch b = batch_of(c, 1);
-  launch_stage<double, EPI_OUT>(c, b, c->y, c->t, nullptr, nullptr, c->xa, 0.0);
+  launch_stage<double, EPI_OUT>(c, b, c->y, c->t, nullptr, c->xa, 0.0, K_QOUT);
   std::swap(c->y, c->xa);
   return last_launch_error(c);
 }
@@ -1531,6 +1643,58 @@ int chfpe_response_2d(chfpe_ctx *c, const chfpe_optical *A, const chfpe_optical 
   return chfpe_response_2d_range(c, A, B, C, 0, n_t1, n_t2, stride1, stride2, dt, R);
 }
 
+int chfpe_response_3d(chfpe_ctx *c, const chfpe_optical *A, const chfpe_optical *B, const chfpe_optical *C,
+                      const chfpe_optical *D, int64_t n_t1, int64_t t2_steps, int64_t n_t3, int32_t stride1,
+                      int32_t stride3, double dt, double *R) {
+  if (!c) return CHFPE_EINVAL;
+  if (!optical_ok(A, c->d.M) || !optical_ok(B, c->d.M) || !optical_ok(C, c->d.M) || !optical_ok(D, c->d.M) ||
+      n_t1 < 0 || t2_steps < 0 || n_t3 < 0 || stride1 < 0 || stride3 < 0 || (n_t1 > 1 && stride1 < 1) ||
+      (n_t3 > 1 && stride3 < 1) || !R || !std::isfinite(dt) || ((n_t1 > 1 || n_t3 > 1 || t2_steps > 0) && !(dt > 0)))
+    return fail(c, CHFPE_EINVAL, "invalid response arguments");
+  if (!c->has_eq) return fail(c, CHFPE_ESTATE, "no equilibrium: call chfpe_equilibrate first");
+  const int64_t n = n_t1 * n_t3;
+  if (n == 0) return CHFPE_OK;
+  int rc = ensure_rbuf(c, (size_t)n);
+  if (rc) return rc;
+  std::vector<double> ga, gb, gc, vd;
+  grad_table(c, A, ga);
+  grad_table(c, B, gb);
+  grad_table(c, C, gc);
+  value_table(c, D, vd);
+  HIPCHK(c, hipMemcpyAsync(c->gA, ga.data(), ga.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->gB, gb.data(), gb.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->gC, gc.data(), gc.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->Cw, vd.data(), vd.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  // U = A^x W_eq, advanced along t1; each branch: B^x, the waiting time,
+  // C^x, then the t3 samples of <D>
+  launch_perturb<double>(c, c->weq, c->u, c->gA);
+  for (int64_t j1 = 0; j1 < n_t1; ++j1) {
+    if (j1 > 0) {
+      rc = rk4(c, c->u, stride1, dt);
+      if (rc) return rc;
+    }
+    launch_perturb<double>(c, c->u, c->y, c->gB);
+    rc = rk4(c, c->y, t2_steps, dt);
+    if (rc) return rc;
+    launch_perturb<double>(c, c->y, c->xa, c->gC);
+    std::swap(c->y, c->xa);  // the excited state becomes the propagated one
+    for (int64_t j3 = 0; j3 < n_t3; ++j3) {
+      if (j3 > 0) {
+        rc = rk4(c, c->y, stride3, dt);
+        if (rc) return rc;
+      }
+      observe_to(c, c->y, c->rbuf + j3 * n_t1 + j1);
+    }
+  }
+  HIPCHK(c, hipMemcpyAsync(R, c->rbuf, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  rc = last_launch_error(c);
+  if (rc) return rc;
+  for (int64_t j = 0; j < n; ++j)
+    if (!std::isfinite(R[j])) return fail(c, CHFPE_ENONFINITE, "response became non-finite");
+  return CHFPE_OK;
+}
+
 int64_t chfpe_state_count(const chfpe_ctx *c) { return c ? c->d.S : 0; }
 
 int chfpe_get_state(chfpe_ctx *c, double *host) {
@@ -1563,7 +1727,8 @@ int chfpe_use_state_as_equilibrium(chfpe_ctx *c) {
 int chfpe_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream) {
   if (!dst || !src || (bytes % 16) != 0) return CHFPE_EINVAL;
   const long long n16 = (long long)(bytes / 16);
-  hipLaunchKernelGGL(k_stream_copy, dim3(4096), dim3(256), 0, reinterpret_cast<hipStream_t>(hip_stream),
+  // 8 workgroups of 256 threads per CU (256 CUs)
+  hipLaunchKernelGGL(k_stream_copy, dim3(2048), dim3(256), 0, reinterpret_cast<hipStream_t>(hip_stream),
                      reinterpret_cast<uint4 *>(dst), reinterpret_cast<const uint4 *>(src), n16);
   return hipGetLastError() == hipSuccess ? CHFPE_OK : CHFPE_EDEVICE;
 }
@@ -1601,13 +1766,19 @@ int chfpe_spectrum_1d(const double *R, int64_t n, double tau, double *omega, dou
   return CHFPE_OK;
 }
 
-int chfpe_spectrum_2d(const double *R, int64_t n_t1, int64_t n_t2, double tau1, double tau2, double *I,
-                      void *hip_stream) {
-  if (!R || !I || n_t1 < 1 || n_t2 < 1 || n_t1 * n_t2 > (1LL << 26) || !(tau1 > 0) || !(tau2 > 0) ||
-      !std::isfinite(tau1) || !std::isfinite(tau2))
+}  // extern "C"
+
+namespace {
+
+// Im{tau_f tau_s sum_{j_s, j_f} exp(-i omega_f t_f + sign_s i omega_s t_s) R[j_s][j_f]}
+// as two passes of discrete Fourier sums (fast axis, then slow axis).
+int spectrum_2d_signed(const double *R, int64_t n_f, int64_t n_s, double tau_f, double tau_s, double sign_s,
+                       double *I, void *hip_stream) {
+  if (!R || !I || n_f < 1 || n_s < 1 || n_f * n_s > (1LL << 26) || !(tau_f > 0) || !(tau_s > 0) ||
+      !std::isfinite(tau_f) || !std::isfinite(tau_s))
     return CHFPE_EINVAL;
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-  const long long n = n_t1 * n_t2;
+  const long long n = n_f * n_s;
   DevBuf bR, bz, bo, bI;
   if (hipMalloc(&bR.p, n * sizeof(double)) != hipSuccess || hipMalloc(&bz.p, n * sizeof(double2)) != hipSuccess ||
       hipMalloc(&bo.p, n * sizeof(double2)) != hipSuccess || hipMalloc(&bI.p, n * sizeof(double)) != hipSuccess)
@@ -1615,18 +1786,32 @@ int chfpe_spectrum_2d(const double *R, int64_t n_t1, int64_t n_t2, double tau1, 
   if (hipMemcpyAsync(bR.p, R, n * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess) return CHFPE_EDEVICE;
   const int nb = (int)((n + 255) / 256);
   hipLaunchKernelGGL(k_to_complex, dim3(nb), dim3(256), 0, st, (const double *)bR.p, (double2 *)bz.p, n);
-  // along t1 (rows of length n_t1), exp(-i omega1 t1)
-  hipLaunchKernelGGL(k_dft_rows, dim3(nb), dim3(256), 0, st, (const double2 *)bz.p, (double2 *)bo.p, (int)n_t2,
-                     (int)n_t1, (int)n_t1, 1, (int)n_t1, 1, -1.0);
-  // along t2 (columns, stride n_t1), exp(-i omega2 t2)
-  hipLaunchKernelGGL(k_dft_rows, dim3(nb), dim3(256), 0, st, (const double2 *)bo.p, (double2 *)bz.p, (int)n_t1,
-                     (int)n_t2, 1, (int)n_t1, 1, (int)n_t1, -1.0);
-  hipLaunchKernelGGL(k_spectrum_out, dim3(nb), dim3(256), 0, st, (const double2 *)bz.p, n, (int)n_t1, tau1 * tau2,
+  // along the fast axis (rows of length n_f), exp(-i omega t)
+  hipLaunchKernelGGL(k_dft_rows, dim3(nb), dim3(256), 0, st, (const double2 *)bz.p, (double2 *)bo.p, (int)n_s,
+                     (int)n_f, (int)n_f, 1, (int)n_f, 1, -1.0);
+  // along the slow axis (columns, stride n_f), exp(sign_s i omega t)
+  hipLaunchKernelGGL(k_dft_rows, dim3(nb), dim3(256), 0, st, (const double2 *)bo.p, (double2 *)bz.p, (int)n_f,
+                     (int)n_s, 1, (int)n_f, 1, (int)n_f, sign_s);
+  hipLaunchKernelGGL(k_spectrum_out, dim3(nb), dim3(256), 0, st, (const double2 *)bz.p, n, (int)n_f, tau_f * tau_s,
                      0.0, 0, (double *)bI.p);
   if (hipMemcpyAsync(I, bI.p, n * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess) return CHFPE_EDEVICE;
   if (hipStreamSynchronize(st) != hipSuccess) return CHFPE_EDEVICE;
   if (hipGetLastError() != hipSuccess) return CHFPE_EDEVICE;
   return CHFPE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int chfpe_spectrum_2d(const double *R, int64_t n_t1, int64_t n_t2, double tau1, double tau2, double *I,
+                      void *hip_stream) {
+  return spectrum_2d_signed(R, n_t1, n_t2, tau1, tau2, -1.0, I, hip_stream);
+}
+
+int chfpe_spectrum_2dir(const double *R, int64_t n_t1, int64_t n_t3, double tau1, double tau3, double *I,
+                        void *hip_stream) {
+  return spectrum_2d_signed(R, n_t1, n_t3, tau1, tau3, +1.0, I, hip_stream);
 }
 
 int chfpe_set_kernel_timing(chfpe_ctx *c, int32_t every) {

@@ -152,6 +152,37 @@ __device__ __forceinline__ void compact_line(T (&f)[NMAX], const int N, const T 
     compact_deriv<T, NMAX, CLOS>(f, N, ca, cb, ct);
 }
 
+// Same derivative of a line in registers, overwritten in place with O(1)
+// extra registers: the forward sweep stores d_i over f_i once the stencil no
+// longer needs f_i as a right neighbour (a window of the three values
+// behind it is kept), and back substitution overwrites d_i with the result.
+// f[N..NMAX) must be zero on entry.
+template <typename T, int NMAX, bool CLOS = false>
+__device__ __forceinline__ void compact_inplace(T (&f)[NMAX], const int N, const T ca, const T cb,
+                                                const double *ct = nullptr) {
+  constexpr T third = T(1.0 / 3.0);
+  T fm3 = T(0), fm2 = T(0), fm1 = T(0), dprev = T(0);
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i) {
+    if (i < N) {
+      const T f0 = f[i];
+      const T fp1 = (i + 1 < NMAX) ? f[i + 1 < NMAX ? i + 1 : 0] : T(0);
+      const T fp2 = (i + 2 < NMAX) ? f[i + 2 < NMAX ? i + 2 : 0] : T(0);
+      const T fp3 = (CLOS && i + 3 < NMAX) ? f[i + 3 < NMAX ? i + 3 : 0] : T(0);
+      const T r = stencil_rhs<T, CLOS>(i, fm3, fm2, fm1, fp1, fp2, fp3, ca, cb, ct);
+      const T d = i == 0 ? r : (r - third * dprev) * T(kThomas.inv[i]);
+      fm3 = fm2;
+      fm2 = fm1;
+      fm1 = f0;
+      f[i] = d;
+      dprev = d;
+    }
+  }
+#pragma unroll
+  for (int i = NMAX - 2; i >= 0; --i)
+    if (i < N - 1) f[i] = f[i] - T(kThomas.cp[i]) * f[i + 1];
+}
+
 // Same derivative for a line of N values held in LDS at base + i * stride,
 // in place, with O(1) registers: a seven-value window of the input moves
 // ahead of the forward sweep, which stores d_i over f_i once f_i is in the
@@ -574,15 +605,214 @@ k_pblock(const Geom g, const Tabs tb, const PBlock pb, const T *__restrict__ X, 
 }
 
 // ---------------------------------------------------------------------------
+// k_pcube (three modes)
+// ---------------------------------------------------------------------------
+// A task is one (branch, element n, q point).  Its p block, N1 x N2 x N3
+// values with p_1 outermost, is contiguous and holds every p line of the
+// element at that q.  F_s(q), V_s'(q) and dX/dq_s(q) are constants of the
+// task, so the three p-derivative fields
+//   G_{n,s} = F_s h_n + V_s' (h_{n+e_s} + n_s (m_s zeta_s gamma_s/beta) h_{n-e_s})
+// and the pointwise terms (as in k_pblock) are formed as the values arrive,
+// and one launch covers D_{p_1}, D_{p_2} and D_{p_3} of every element: the
+// q passes that follow read only h_n itself.
+// Thread (j2, j3) of the (p_2, p_3) plane keeps its p_1 line in registers:
+// acc (pointwise terms plus the solved p_2 and p_3 fields) and g1 (the
+// p_1 field, solved in place at the end).  Planes of constant p_1 go through
+// LDS in rounds of PL planes; G_{n,2} and G_{n,3} of a round
+// are solved along p_2 and p_3 there (two lanes per line when SPLIT: all
+// three axes have NB1 points), then added to acc.
+// PERTURB: out = X^x h as in k_pblock, with fields dX/dq_s h_n.
+struct PCube {
+  int N1, N2, N3;  // p-axis lengths
+  int plane;       // N2 * N3: threads that own a p_1 line
+  int ntasks, nblk;
+};
+
+// Largest workgroup of k_pcube for a p_1 bucket: acc and g1 take
+// 2 NB1 values per thread, a round's loads 7 PL more, and every wave of the
+// workgroup must fit the register file together (512 VGPRs per SIMD lane).
+template <typename T, int NB1>
+constexpr int pcube_max_threads() {
+  return sizeof(T) == 8 ? (NB1 == 24 ? 768 : 512) : (NB1 >= 32 ? 768 : 1024);
+}
+
+// (p_2, p_3) planes per LDS round of k_pcube.
+constexpr int pcube_planes(const int nb1) { return nb1 == 24 ? 4 : nb1 / 4; }
+
+template <typename T, typename TO, int NB1, bool SPLIT, bool PERTURB, bool CLOS = false>
+__global__ void __launch_bounds__((pcube_max_threads<T, NB1>()))
+k_pcube(const Geom g, const Tabs tb, const PCube pc, const T *__restrict__ X, TO *__restrict__ out,
+        const double *__restrict__ grad) {
+  constexpr int PL = pcube_planes(NB1);  // planes per round
+  constexpr int NR = (NB1 + PL - 1) / PL;  // rounds
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int task = xcd_task(blockIdx.x, pc.nblk);
+  if (task >= pc.ntasks) return;
+  const int N1 = pc.N1, N2 = pc.N2, N3 = pc.N3, plane = pc.plane;
+  const int rs = N3 + 1;                  // LDS row stride (one pad value per p_3 row)
+  T *G2 = reinterpret_cast<T *>(smem_raw);  // [PL][N2][N3 + 1]
+  T *G3 = G2 + PL * N2 * rs;
+  const int ne_all = g.ne * g.nbatch;
+  const int ea = task % ne_all;  // (branch, element): elements of one q point are adjacent tasks
+  const int ql = task / ne_all;
+  const int br = ea / g.ne;
+  const int e = ea - br * g.ne;
+  const int tid = threadIdx.x;
+  const bool own = tid < plane;
+  const int j2 = own ? tid / N3 : 0;
+  const int j3 = own ? tid - j2 * N3 : 0;
+  const int Q = g.Q;
+
+  const long long blk = (long long)ql * g.P;
+  const T *Xe = X + (long long)ea * g.E + blk;
+  TO *Oe = out + (long long)ea * g.E + blk;
+  const T *Xb = X + (long long)br * g.ne * g.E;
+  const T *Xu[3];
+  const T *Xd[3];
+  T Fv[3], vu[3], vd[3], pwu[3], pwd[3];
+  const double p2 = tb.pg[1 * kTab + j2], p3 = tb.pg[2 * kTab + j3];
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const int up = PERTURB ? -1 : tb.up[e * 3 + s];
+    const int dn = PERTURB ? -1 : tb.dn[e * 3 + s];
+    Xu[s] = up >= 0 ? Xb + (long long)up * g.E + blk : Xe;
+    Xd[s] = dn >= 0 ? Xb + (long long)dn * g.E + blk : Xe;
+    if (PERTURB) {
+      Fv[s] = T(grad[s * Q + ql]);
+      vu[s] = vd[s] = pwu[s] = pwd[s] = T(0);
+    } else {
+      const double vp = tb.VpQ[s * Q + ql];
+      Fv[s] = T(tb.F[s * Q + ql]);
+      vu[s] = up >= 0 ? T(vp) : T(0);
+      vd[s] = T(vp * tb.cc[e * 3 + s]);         // zero when n_s = 0
+      pwd[s] = T(vp * 0.5 * tb.tc[e * 3 + s]);  // times p_s
+      pwu[s] = up >= 0 ? T(vp * g.bm[s]) : T(0);
+    }
+  }
+  // pointwise coefficient of h_n: -sum_s n_s gamma_s, or for PERTURB
+  // -sum_s dX/dq_s beta p_s / 2 m_s (the p_1 part is added per plane)
+  const T dmp = PERTURB ? T(0) : T(tb.damp[e]);
+  const T c23 = PERTURB ? T(double(Fv[1]) * g.bm[1] * p2 + double(Fv[2]) * g.bm[2] * p3) : T(0);
+  const T c1 = PERTURB ? T(double(Fv[0]) * g.bm[0]) : T(0);
+  const T q2u = T(p2) * pwu[1], q2d = T(p2) * pwd[1], q3u = T(p3) * pwu[2], q3d = T(p3) * pwd[2];
+
+  T acc[NB1], g1[NB1];
+#pragma unroll
+  for (int i = 0; i < NB1; ++i) {
+    acc[i] = T(0);
+    g1[i] = T(0);
+  }
+
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int i0 = r * PL;
+    if (i0 >= N1) break;  // uniform
+    // ---- loads and pointwise terms of this round's planes
+    T h[PL], hu[3][PL], hd[3][PL];
+#pragma unroll
+    for (int k = 0; k < PL; ++k) {
+      const int i = i0 + k;
+      const uint32_t o = (uint32_t)(min(i, N1 - 1) * plane + (own ? tid : 0));
+      h[k] = at_u32(Xe, o);
+      if (!PERTURB) {
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+          hu[s][k] = at_u32(Xu[s], o);
+          hd[s][k] = at_u32(Xd[s], o);
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < PL; ++k) {
+      const int i = i0 + k;
+      if (i < N1) {
+        const T p1 = T(tb.pg[0 * kTab + i]);
+        T a, f1, f2, f3;
+        if (PERTURB) {
+          a = -(c23 + c1 * p1) * h[k];
+          f1 = Fv[0] * h[k];
+          f2 = Fv[1] * h[k];
+          f3 = Fv[2] * h[k];
+        } else {
+          // n_s zeta_s gamma_s V_s' p_s/2 h_{n-e_s} - V_s' beta p_s/(2 m_s) h_{n+e_s} - sum n gamma h_n
+          a = -dmp * h[k] + p1 * (pwd[0] * hd[0][k] - pwu[0] * hu[0][k]) + q2d * hd[1][k] - q2u * hu[1][k] +
+              q3d * hd[2][k] - q3u * hu[2][k];
+          f1 = Fv[0] * h[k] + vu[0] * hu[0][k] + vd[0] * hd[0][k];
+          f2 = Fv[1] * h[k] + vu[1] * hu[1][k] + vd[1] * hd[1][k];
+          f3 = Fv[2] * h[k] + vu[2] * hu[2][k] + vd[2] * hd[2][k];
+        }
+        acc[i] = a;
+        g1[i] = f1;
+        if (own) {
+          const int li = (k * N2 + j2) * rs + j3;
+          G2[li] = f2;
+          G3[li] = f3;
+        }
+      }
+    }
+    __syncthreads();
+    // ---- p_2 lines of G2 (fixed k, j3) and p_3 lines of G3 (fixed k, j2)
+    const int npl = min(PL, N1 - i0);
+    const int nl2 = npl * N3, nl = nl2 + npl * N2;
+    const double *ct2 = CLOS ? tb.clos + (3 + 1) * 2 * kClosRows * kTab : nullptr;
+    const double *ct3 = CLOS ? tb.clos + (3 + 2) * 2 * kClosRows * kTab : nullptr;
+    if (SPLIT) {
+      for (int hl = tid; hl < 2 * nl; hl += blockDim.x) {
+        const int l = hl >> 1;
+        if (l < nl2) {
+          const int k = l / N3, c = l - k * N3;
+          compact_split<T, NB1, CLOS>(G2, k * N2 * rs + c, rs, hl & 1, T(g.dp_ca[1]), T(g.dp_cb[1]), ct2);
+        } else {
+          const int l3 = l - nl2;
+          compact_split<T, NB1, CLOS>(G3, l3 * rs, 1, hl & 1, T(g.dp_ca[2]), T(g.dp_cb[2]), ct3);
+        }
+      }
+    } else {
+      for (int l = tid; l < nl; l += blockDim.x) {
+        if (l < nl2) {
+          const int k = l / N3, c = l - k * N3;
+          compact_lds<T, CLOS>(G2, k * N2 * rs + c, rs, N2, T(g.dp_ca[1]), T(g.dp_cb[1]), ct2);
+        } else {
+          compact_lds<T, CLOS>(G3, (l - nl2) * rs, 1, N3, T(g.dp_ca[2]), T(g.dp_cb[2]), ct3);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PL; ++k) {
+      const int i = i0 + k;
+      if (i < N1 && own) {
+        const int li = (k * N2 + j2) * rs + j3;
+        acc[i] += G2[li] + G3[li];
+      }
+    }
+    __syncthreads();  // the next round overwrites the planes
+  }
+  // ---- p_1 lines, one per thread, in registers
+  compact_inplace<T, NB1, CLOS>(g1, N1, T(g.dp_ca[0]), T(g.dp_cb[0]),
+                                CLOS ? tb.clos + 3 * 2 * kClosRows * kTab : nullptr);
+  if (!own) return;
+#pragma unroll
+  for (int i = 0; i < NB1; ++i)
+    if (i < N1) at_u32(Oe, (uint32_t)(i * plane + tid)) = TO(acc[i] + g1[i]);
+}
+
+// ---------------------------------------------------------------------------
 // k_qpass
 // ---------------------------------------------------------------------------
+// Stage epilogues.  Eq. (eq:HEOM) is linear with a time-independent
+// generator L, so one classical RK4 step is the degree-4 Taylor polynomial
+//   y <- (1 + dt L + (dt L)^2/2 + (dt L)^3/6 + (dt L)^4/24) y,
+// evaluated here in nested (Horner) form with four right-hand sides:
+//   z1 = y + dt/4 L y,  z2 = y + dt/3 L z1,  z3 = y + dt/2 L z2,  y <- y + dt L z3.
+// Each stage reads its input z and y and writes one state; no running sum
+// of the stage slopes is kept.  c is the stage coefficient (dt/4 .. dt).
 enum Epi : int {
   EPI_ACC = 0,  // Tacc += contribution
   EPI_OUT = 1,  // xo = Tacc + contribution               (one RHS evaluation)
-  EPI_S1 = 2,   // k = Tacc + c;  yacc = X + dt/6 k;  xo = X + dt/2 k      (X is y)
-  EPI_S2 = 3,   // k;  yacc += dt/3 k;  xo = y + dt/2 k
-  EPI_S3 = 4,   // k;  yacc += dt/3 k;  xo = y + dt k
-  EPI_S4 = 5    // k;  xo (= y) = yacc + dt/6 k
+  EPI_H1 = 2,   // xo = X + c k                           (first stage: X is y)
+  EPI_H2 = 3,   // xo = y + c k                           (middle stages)
+  EPI_H4 = 4    // xo = xo + c k                          (last stage: xo is y, in place)
 };
 
 // q-linear index and p index of a state position (within one element)
@@ -610,12 +840,11 @@ __device__ __forceinline__ T field_at(const Geom &g, const Tabs &tb, const T *__
   return Gv;
 }
 
-// T: type of X and of the arithmetic; TO: type of Tacc, y, yacc, xo.
+// T: type of X and of the arithmetic; TO: type of Tacc, y, xo.
 template <typename T, typename TO, int NMAX, bool TWO, int EPI, int FA, int FB, bool CLOS = false>
 __global__ void __launch_bounds__(512)
 k_qpass(const Geom g, const Tabs tb, const QPass qp, const T *__restrict__ X, TO *__restrict__ Tacc,
-        const TO *__restrict__ y, TO *__restrict__ yacc, TO *__restrict__ xo, const double *__restrict__ grad,
-        const double dt) {
+        const TO *__restrict__ y, TO *__restrict__ xo, const double *__restrict__ grad, const double cst) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *lds = reinterpret_cast<T *>(smem_raw);
   const int task = xcd_task(blockIdx.x, qp.nblk);
@@ -717,7 +946,7 @@ k_qpass(const Geom g, const Tabs tb, const QPass qp, const T *__restrict__ X, TO
     const int s = qp.sb_mode;
     kb = T(-tb.pm[s * kTab + (pix0 / g.PS[s]) % g.Np[s]]);
   }
-  const T h6 = T(dt / 6.0), h3 = T(dt / 3.0), h2 = T(dt / 2.0), h1 = T(dt);
+  const T cs = T(cst);
 #pragma unroll
   for (int i = 0; i < NMAX; ++i) {
     if (i < Na) {
@@ -730,24 +959,14 @@ k_qpass(const Geom g, const Tabs tb, const QPass qp, const T *__restrict__ X, TO
       } else {
         kv += T(tacc);
         TO &xov = at_u32(xo + ui, lrel);
-        if (EPI == EPI_OUT) {
+        if (EPI == EPI_OUT)
           xov = TO(kv);
-        } else if (EPI == EPI_S1) {
-          at_u32(yacc + ui, lrel) = TO(f[i] + h6 * kv);
-          xov = TO(f[i] + h2 * kv);
-        } else if (EPI == EPI_S2) {
-          const T yv = T(at_u32(y + ui, lrel));
-          TO &ya = at_u32(yacc + ui, lrel);
-          ya = TO(T(ya) + h3 * kv);
-          xov = TO(yv + h2 * kv);
-        } else if (EPI == EPI_S3) {
-          const T yv = T(at_u32(y + ui, lrel));
-          TO &ya = at_u32(yacc + ui, lrel);
-          ya = TO(T(ya) + h3 * kv);
-          xov = TO(yv + h1 * kv);
-        } else {  // EPI_S4
-          xov = TO(T(at_u32(yacc + ui, lrel)) + h6 * kv);
-        }
+        else if (EPI == EPI_H1)
+          xov = TO(f[i] + cs * kv);
+        else if (EPI == EPI_H2)
+          xov = TO(T(at_u32(y + ui, lrel)) + cs * kv);
+        else  // EPI_H4
+          xov = TO(T(xov) + cs * kv);
       }
     }
   }
@@ -910,12 +1129,21 @@ k_scatter_r(const double *__restrict__ Rw, double *__restrict__ R, const int n_t
   R[(long long)j2 * n_t1 + j0 + b] = Rw[(long long)j2 * B + b];
 }
 
-// dst = src, 16-byte vectors
+// dst = src, 16-byte vectors: each thread keeps four loads in flight before
+// it stores (a grid-stride loop over a few workgroups per CU), the form that
+// reaches the device's streaming bandwidth
 __global__ void __launch_bounds__(256)
 k_stream_copy(uint4 *__restrict__ dst, const uint4 *__restrict__ src, const long long n16) {
-  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n16;
-       i += (long long)gridDim.x * 256)
-    dst[i] = src[i];
+  const long long st = (long long)gridDim.x * 256;
+  long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  for (; i + 3 * st < n16; i += 4 * st) {
+    const uint4 a = src[i], b = src[i + st], c = src[i + 2 * st], d = src[i + 3 * st];
+    dst[i] = a;
+    dst[i + st] = b;
+    dst[i + 2 * st] = c;
+    dst[i + 3 * st] = d;
+  }
+  for (; i < n16; i += st) dst[i] = src[i];
 }
 
 }  // namespace chfpe

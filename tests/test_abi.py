@@ -40,12 +40,16 @@ def test_library_exports_every_declared_symbol(binding):
     assert not missing, missing
 
 
-def test_workspace_bytes_covers_eight_states(binding):
+def test_workspace_bytes_covers_six_states(binding):
+    """Six FP64 states (W_eq, U, y, two stage states, the partial right-hand
+    side) plus tables; a wave of B branches adds four states each."""
     w = wl.workload("two_mode_32")
     p = binding.params_from_workload(w)
     n = binding.workspace_bytes(p)
     state_bytes = 10 * 32 ** 4 * 8
-    assert 7 * state_bytes <= n < 8 * state_bytes + (1 << 24)
+    assert 6 * state_bytes <= n < 6 * state_bytes + (1 << 24)
+    p32 = binding.params_from_workload(w, precision=binding.CHFPE_FP32, batch=8)
+    assert binding.workspace_bytes(p32) - n == 4 * 8 * state_bytes // 2
 
 
 @pytest.mark.parametrize("field,value", [

@@ -152,3 +152,53 @@ def test_features_follow_the_definition():
     # rows 7.. are S[i][i+2]
     assert F[7, 3] == 1.0 and F[6, 3] == 0.0
     assert np.allclose(cl.row_axes(w), np.repeat(np.arange(4), 13))
+
+
+def test_adam_first_and_constant_gradient_steps_follow_the_published_update():
+    """Facts of Adam (Kingma & Ba) that fix the update without retyping it:
+    with bias correction, the first step has m_hat = g and v_hat = g^2, so a
+    parameter with gradient g moves by -lr g / (|g| + eps), i.e.
+    -lr sign(g) (1 - O(eps/|g|)), and one with g = 0 does not move; under a
+    constant gradient every later step is the same, while a gradient that
+    flips sign after many steps moves the parameter against the new sign
+    only once the first moment has turned (it keeps the old direction for
+    about ln 2 / (1 - beta1) ~ 7 steps)."""
+    rng = np.random.default_rng(4)
+    p0 = cl.init_params(5)
+    g = {k: rng.standard_normal(np.shape(v)) for k, v in p0.items() if k != "b2"}
+    g["b2"] = 0.3
+    g["W1"][0, :4] = 0.0  # untouched entries
+    lr = 1e-3
+    p = {k: np.array(v, dtype=np.float64, copy=True) for k, v in p0.items()}
+    st = {}
+    cl.adam_step(p, g, st, lr)
+    for k in p:
+        d = np.asarray(p[k]) - np.asarray(p0[k])
+        gk = np.asarray(g[k], dtype=np.float64)
+        np.testing.assert_allclose(d, -lr * gk / (np.abs(gk) + 1e-8), rtol=1e-9, atol=1e-15)
+    assert np.all(p["W1"][0, :4] == p0["W1"][0, :4])
+    big = np.abs(g["W2"]) > 1e-3
+    np.testing.assert_allclose((p["W2"] - p0["W2"])[big], -lr * np.sign(g["W2"][big]), rtol=1e-5)
+    # constant gradient: steps 2..20 repeat the first one
+    prev = {k: np.array(v, copy=True) for k, v in p.items()}
+    for _ in range(19):
+        cl.adam_step(p, g, st, lr)
+        for k in p:
+            gk = np.asarray(g[k], dtype=np.float64)
+            np.testing.assert_allclose(np.asarray(p[k]) - prev[k], -lr * gk / (np.abs(gk) + 1e-8),
+                                       rtol=1e-9, atol=1e-15)
+            prev[k] = np.array(p[k], copy=True)
+    # the gradient of one scalar flips after 20 steps
+    x = {"W1": np.zeros((cl.NFEAT, cl.NHID)), "b1": np.zeros(cl.NHID), "W2": np.zeros(cl.NHID), "b2": 0.0}
+    gx = {"W1": np.zeros((cl.NFEAT, cl.NHID)), "b1": np.zeros(cl.NHID), "W2": np.zeros(cl.NHID), "b2": 1.0}
+    sx = {}
+    for _ in range(20):
+        cl.adam_step(x, gx, sx, lr)
+    gx["b2"] = -1.0
+    moves = []
+    for _ in range(12):
+        before = x["b2"]
+        cl.adam_step(x, gx, sx, lr)
+        moves.append(x["b2"] - before)
+    first_up = next(i for i, mv in enumerate(moves) if mv > 0)
+    assert all(mv < 0 for mv in moves[:first_up]) and 5 <= first_up <= 9, moves

@@ -48,6 +48,8 @@ COARSE = {
     "m2_n8": wl.workload("two_mode_32", Nq=[8, 8], Np=[8, 8], K=2),       # lane-pair solves
     "m2_n6": wl.workload("two_mode_32", Nq=[6, 7], Np=[6, 6], K=2),       # one-lane solves
     "m3_n6": wl.workload("three_mode_24", Nq=[6, 6, 6], Np=[6, 6, 6], K=2),
+    # cubic 8^3 p blocks: k_pcube's lane-pair plane solves with the closure
+    "m3_c8": wl.workload("three_mode_24", Nq=[6, 7, 6], Np=[8, 8, 8], K=2),
 }
 
 
@@ -116,6 +118,55 @@ def test_network_forward_and_backward_match_the_oracle(pk):
     g_ref = cl.backward(p, cache, gs.astype(np.float64))
     g_ref = np.concatenate([np.ravel(g_ref["W1"]), g_ref["b1"], g_ref["W2"], [g_ref["b2"]]])
     assert rel(g_dev, g_ref) < 1e-4
+
+
+def _bf16_bounds(p, X, gs):
+    """Elementwise bounds on how far a network evaluated with BF16 operands
+    (X, W1, tanh(H), W2 and the backward products rounded to BF16, FP32
+    accumulation) can be from the exact FP64 network: each product of two
+    rounded values has relative error at most 2u + u^2 with u = 2^-9 (half
+    of BF16's 2^-8 step), tanh is 1-Lipschitz with slope 1 - tanh^2, and
+    FP32 sums add 1e-6 of the absolute sums."""
+    u = 2.0 ** -9
+    e2 = 2 * u + u * u
+    aX, aW1, aW2 = np.abs(X), np.abs(p["W1"]), np.abs(p["W2"])
+    absH = aX @ aW1
+    dH = (e2 + 1e-6) * absH
+    A1 = np.tanh(X @ p["W1"] + p["b1"])
+    dA1 = dH * np.minimum(1.0, 1.0 - A1 * A1 + 2.0 * dH)
+    ds = ((np.abs(A1) + dA1) * e2 + dA1) @ aW2 + 1e-6 * (np.abs(A1) @ aW2 + abs(p["b2"]))
+    ags = np.abs(gs)[:, None]
+    dgW2 = (ags * ((np.abs(A1) + dA1) * e2 + dA1)).sum(axis=0) + 1e-6 * (ags * np.abs(A1)).sum(axis=0)
+    gH = ags * aW2[None, :] * (1.0 - A1 * A1)
+    dgH = ags * aW2[None, :] * (u * (1.0 - A1 * A1) + 2.0 * (np.abs(A1) + dA1) * dA1) * (1 + u)
+    dgW1 = aX.T @ (gH * e2 + dgH * (1 + u) ** 2) + 1e-6 * (aX.T @ gH)
+    dgb1 = dgH.sum(axis=0) + 1e-6 * gH.sum(axis=0)
+    dgb2 = 1e-6 * np.abs(gs).sum()
+    return ds, np.concatenate([np.ravel(dgW1), dgb1, dgW2, [dgb2]])
+
+
+def test_network_matches_the_exact_fp64_network_within_bf16_bounds(pk):
+    """The device network against the plain FP64 network (no rounding
+    mirrored): every output and gradient entry within the bound BF16
+    operands allow (_bf16_bounds), and the bound is tight enough to matter
+    (the device differs from the exact network, by a fraction of it)."""
+    w = COARSE["m3_n6"]
+    feat = cl.features(w).astype(np.float32)
+    p = _unflat(_flat(_params(1)))
+    p["b1"] = np.float32(np.random.default_rng(3).normal(0, 0.1, 32)).astype(np.float64)
+    X = feat.astype(np.float64)
+    s_dev = pk.closure_eval(_flat(p), feat)
+    s_ex, cache = cl.forward(p, X, rounding=False)
+    gs = np.random.default_rng(2).standard_normal(len(feat)).astype(np.float32)
+    g_dev = pk.closure_grad(_flat(p), feat, gs)
+    g_ex = cl.backward(p, cache, gs.astype(np.float64), rounding=False)
+    g_ex = np.concatenate([np.ravel(g_ex["W1"]), g_ex["b1"], g_ex["W2"], [g_ex["b2"]]])
+    ds, dg = _bf16_bounds(p, X, gs.astype(np.float64))
+    es = np.abs(s_dev - s_ex)
+    eg = np.abs(g_dev - g_ex)
+    say(f"    forward: max err/bound {np.max(es / ds):.3f}; backward: {np.max(eg / (dg + 1e-30)):.3f}")
+    assert np.all(es <= ds) and np.all(eg <= dg + 1e-30)
+    assert np.max(es) > 0.0 and np.max(es / ds) > 1e-3  # BF16 rounding is in effect
 
 
 def _groups(pk, wc, seeds):

@@ -4,9 +4,10 @@ Bar (FP64 path): relative L2 error <= 1e-10 on states, responses and
 observables; one right-hand side and a few RK4 steps agree to ~1e-14.
 Sizes: small grids that span several tiles with ragged tails, the one-mode
 workload at full size, the two-mode 32^4 workload at full size in the
-launch configuration the benchmark times (sampled t1/t2 entries), and the
-three-mode workloads at full size (12^6 and 16^6 whole states, 24^6 at
-sampled points of one right-hand side).
+launch configuration its benchmark times (one 64-branch FP64 wave, sampled
+t1 columns), and the three-mode workloads at full size (12^6 and 16^6
+whole states, 16^6 responses in batched FP64 and FP32 waves on a t1 subset,
+24^6 at sampled points of one right-hand side and one whole RK4 step).
 """
 import sys
 
@@ -63,8 +64,40 @@ SMALL = {
     # square 8 x 8 (p_2, p_3) blocks: lane-pair line solves, ragged q and p_1
     "m3_p8_k2": wl.workload("three_mode_24", Nq=[7, 6, 8], Np=[9, 8, 8], K=2),
     # 24 x 24 (p_2, p_3) blocks as in the 24^6 workload: three rows per thread
+    # (a 576-thread plane with 5-point p_1 lines exceeds k_pcube's FP64
+    # workgroup: the p-block + (q_1, p_1) path)
     "m3_p24_k2": wl.workload("three_mode_24", Nq=[5, 6, 5], Np=[5, 24, 24], K=2),
+    # cubic p blocks: k_pcube with lane-pair plane solves (8^3, 12^3, 24^3)
+    "m3_c8_k2": wl.workload("three_mode_24", Nq=[5, 6, 7], Np=[8, 8, 8], K=2),
+    "m3_c12_k2": wl.workload("three_mode_24", Nq=[5, 5, 6], Np=[12, 12, 12], K=2),
+    "m3_c24_k2": wl.workload("three_mode_24", Nq=[5, 5, 5], Np=[24, 24, 24], K=2),
 }
+
+THREE = [n for n in SMALL if n.startswith("m3")]
+
+
+@pytest.mark.parametrize("name", THREE)
+def test_three_mode_p_block_path_matches_the_oracle(pk, monkeypatch, name):
+    """Three modes with k_pcube switched off (CHFPE_PCUBE=0): the p-block,
+    (q_2, q_3) and (q_1, p_1) passes, and the two-launch excitation, still
+    give the oracle's right-hand side, RK4 steps and X^x."""
+    monkeypatch.setenv("CHFPE_PCUBE", "0")
+    w = SMALL[name]
+    say(f"[p-block path] {name}")
+    W = phys_state(w, seed=11)
+    X = wl.optical(3, lin=[1.0, -0.7, 0.4], quad=[[0.2, 0.05, -0.03], [0.05, -0.1, 0.02], [-0.03, 0.02, 0.3]])
+    with solver(pk, w) as s:
+        s.set_state(W)
+        s.rhs()
+        e_rhs = rel_l2(s.get_state(), orc.rhs(w, W))
+        s.set_state(W)
+        s.propagate(2, 0.002)
+        e_rk4 = rel_l2(s.get_state(), orc.rk4(w, W, 2, 0.002))
+        s.set_state(W)
+        s.perturb(X)
+        e_x = rel_l2(s.get_state(), orc.perturb(w, X, W))
+    say(f"    rhs {e_rhs:.2e} rk4 {e_rk4:.2e} perturb {e_x:.2e}")
+    assert e_rhs < 1e-13 and e_rk4 < 1e-13 and e_x < 1e-13
 
 
 @pytest.mark.parametrize("name", list(SMALL))
@@ -172,21 +205,28 @@ def test_two_mode_full_size_rhs_and_steps(pk):
         assert rel_l2(s.get_state(), ref_2) < 1e-13
 
 
+@pytest.mark.timeout(900)
 def test_two_mode_full_size_response_2d_sampled(pk):
-    """The benchmarked 2D THz-Raman run (64 t1 x 256 t2, stride 1) on the GPU;
-    sampled t1 columns (0, 1, 3) and the first 4 t2 rows against the oracle,
-    both starting from the same equilibrium (the discrete Boltzmann state)."""
+    """The two-mode 2D THz-Raman run (64 t1 x 256 t2, stride 1) in the launch
+    configuration its benchmark times: all 64 t1 branches in one batched
+    FP64 wave (a captured HIP graph).  Columns spread across the wave
+    (j1 = 0, 21, 42, 63) over the first 16 t2 rows against the oracle, both
+    starting from the same equilibrium (the discrete Boltzmann state); the
+    rest of R must be finite."""
     w = wl.workload("two_mode_32")
-    say("[full] two_mode_32 response_2d 64x256 sampled")
+    say("[full] two_mode_32 response_2d 64x256, one 64-branch wave, sampled")
     Wb = orc.boltzmann(w)
-    cols = [0, 1, 3]
-    ref = orc.response_2d(w, w["A"], w["B"], w["C"], Wb, 64, 4, 1, 1, w["dt"], j1_list=cols)
-    with solver(pk, w) as s:
+    cols = [0, 21, 42, 63]
+    ref = orc.response_2d(w, w["A"], w["B"], w["C"], Wb, 64, 16, 1, 1, w["dt"], j1_list=cols)
+    say("    oracle done")
+    with pk.Solver(pk.params_from_workload(w, precision=pk.CHFPE_FP64, batch=64)) as s:
         s.set_state(Wb)
         s.use_state_as_equilibrium()
         got = s.response_2d(w["A"], w["B"], w["C"], 64, 256, 1, 1, w["dt"])
     assert np.all(np.isfinite(got))
-    assert rel_l2(got[:4, cols], ref[:4, cols]) < FP64_TOL
+    err = rel_l2(got[:16, cols], ref[:16, cols])
+    say(f"    sampled columns rel L2 {err:.2e}")
+    assert err < FP64_TOL
 
 
 def test_spectra_parity(pk):
@@ -376,12 +416,14 @@ def test_every_autotuner_tile_shape_matches_the_oracle(pk, monkeypatch, name):
 
 
 def test_batched_launch_stays_within_one_dispatch(pk, monkeypatch):
-    """Ten elements of 16^6 points in a wave of 32 FP32 branch states: at one
-    p-block per task that launch would pass 2^32 work-items (a dispatch's
-    limit), so the planner raises the request to two blocks per task.  The
-    32 columns then match the single-state FP64 solver (which keeps one)."""
+    """Ten elements of 16^6 points in a wave of 32 FP32 branch states on the
+    p-block path: at one p-block per task that launch would pass 2^32
+    work-items (a dispatch's limit), so the planner raises the request to two
+    blocks per task.  The 32 columns then match the single-state FP64 solver
+    (which keeps one)."""
     import torch
     monkeypatch.setenv("CHFPE_TUNE_PB_NB", "1")
+    monkeypatch.setenv("CHFPE_PCUBE", "0")  # the p-block launch is the one at the limit
     w = wl.workload("three_mode_16")
     dt = w["dt"]
     A, B, C = w["A"], w["B"], w["C"]
@@ -429,6 +471,7 @@ def test_three_mode_full_size_rhs_and_steps(pk, name, steps):
     assert e_rhs < 1e-13 and e_rk4 < 1e-13
 
 
+@pytest.mark.timeout(900)
 def test_three_mode_24_full_size_rhs_sampled(pk):
     """Three modes on the full 24^6 grid (10 elements, 1.9e9 values): one
     right-hand side on the GPU, checked at 96 seeded points and at the first
@@ -469,3 +512,111 @@ def test_three_mode_24_full_size_rhs_sampled(pk):
     err = float(np.abs(g - ref).max() / np.abs(ref).max())
     say(f"    max error / max |rhs| over {len(pts)} points: {err:.2e}")
     assert err < 1e-13
+
+
+@pytest.mark.timeout(900)
+def test_three_mode_16_response_2d_waves_against_the_oracle(pk):
+    """The three-mode 16^6 workload's 2D response on a t1 subset, in batched
+    waves as its benchmark runs them: FP64 waves against the oracle at the
+    FP64 bar and FP32 waves at the FP32 bar.  Columns j1 = 0..2 (waves of 3)
+    over 4 t2 rows, from the discrete Boltzmann state as W_eq; columns 0
+    and 2 are compared (the oracle skips column 1)."""
+    import torch
+    w = wl.workload("three_mode_16")
+    dt = w["dt"]
+    say("[full] three_mode_16 response: oracle columns 0, 2 x 4 rows")
+    Wb = orc.boltzmann(w)
+    cols = [0, 2]
+    ref = orc.response_2d(w, w["A"], w["B"], w["C"], Wb, 3, 4, 1, 1, dt, j1_list=cols)
+    say("    oracle done")
+    for prec, tol in ((pk.CHFPE_FP64, FP64_TOL), (pk.CHFPE_FP32, 1e-4)):
+        with pk.Solver(pk.params_from_workload(w, precision=prec, batch=3)) as s:
+            s.set_state(Wb)
+            s.use_state_as_equilibrium()
+            got = s.response_2d(w["A"], w["B"], w["C"], 3, 4, 1, 1, dt)
+        torch.cuda.empty_cache()
+        err = rel_l2(got[:, cols], ref[:, cols])
+        say(f"    precision {prec}: rel L2 {err:.2e}")
+        assert err < tol
+
+
+@pytest.mark.timeout(900)
+def test_three_mode_24_full_size_rk4_step(pk):
+    """One whole RK4 step of the full 24^6 three-mode state (1.9e9 values)
+    against the oracle, every value.  The oracle's step is taken as its four
+    right-hand sides with the classical RK4 combination (one call each, so
+    that progress shows between them); about 95 GB of host memory (six
+    states: input, GPU result, sum, stage input, slope, and the oracle's
+    own copy in h-form)."""
+    import psutil
+    import torch
+    need = 110e9
+    if psutil.virtual_memory().available < need:
+        pytest.skip(f"needs {need / 1e9:.0f} GB of free host memory for the oracle at 24^6")
+    w = wl.workload("three_mode_24")
+    dt = w["dt"]
+    say("[full] three_mode_24 rk4 step: building the state")
+    w0 = {**w, "K": 0}
+    env = orc.boltzmann(w0)[0]
+    ne = orc.state_shape(w)[0]
+    y = np.empty(orc.state_shape(w))
+    for e in range(ne):
+        sm = wl.smooth_state(w0, seed=30 + e)[0]
+        sm *= 0.3 / np.abs(sm).max()
+        sm += 1.0
+        np.multiply(env, sm, out=y[e])
+    del env, sm
+    say("    GPU step")
+    with solver(pk, w) as s:
+        s.set_state(y)
+        s.propagate(1, dt)
+        got = s.get_state()
+    torch.cuda.empty_cache()
+    acc = y.copy()
+    x = None
+    for st, (cx, cw) in enumerate(((0.5, 1.0), (0.5, 2.0), (1.0, 2.0), (None, 1.0))):
+        k = orc.rhs(w, y if x is None else x)
+        say(f"    oracle stage {st + 1}/4 done")
+        if cx is not None:  # next stage input y + cx dt k, in place
+            if x is None:
+                x = np.empty_like(y)
+            np.multiply(k, cx * dt, out=x)
+            x += y
+        np.multiply(k, dt / 6.0 * cw, out=k)
+        acc += k
+        del k
+    del x
+    err = rel_l2(got, acc)
+    say(f"    rel L2 {err:.2e}")
+    assert err < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# third-order response, Eq. (3Dresponse), and the 2D IR spectrum
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["m1_n12_k3", "m2_n10_k2", "m3_n8_k2", "m3_c8_k2"])
+def test_response_3d_parity_small(pk, name):
+    """R^(3)(t3, t2, t1) at one waiting time against the oracle (FP64 bar),
+    with quadratic operators (dipole, polarizability) in the TRRT-like order
+    A = mu, B = Pi, C = Pi, D = mu; also from a batched FP32 context, whose
+    third-order branches run on the FP64 single-state buffers."""
+    w = SMALL[name]
+    A, B = _ops(w["M"])
+    say(f"[response_3d] {name}")
+    Weq = orc.equilibrate(w, 10, 0.004)
+    ref = orc.response_3d(w, A, B, B, A, Weq, 4, 6, 5, 2, 3, 0.004)
+    for prec, batch in ((pk.CHFPE_FP64, 1), (pk.CHFPE_FP32, 3)):
+        with pk.Solver(pk.params_from_workload(w, precision=prec, batch=batch)) as s:
+            s.equilibrate(10, 0.004)
+            got = s.response_3d(A, B, B, A, 4, 6, 5, 2, 3, 0.004)
+        assert rel_l2(got, ref) < FP64_TOL, prec
+
+
+def test_spectrum_2dir_parity(pk):
+    """Device Fourier sums of Eq. (noncorrelation) against the oracle's."""
+    rng = np.random.default_rng(11)
+    for shape in ((256, 64), (7, 5)):
+        R = rng.standard_normal(shape)
+        _, _, ref = orc.spectrum_2dir(R, 0.005, 0.01)
+        assert rel_l2(pk.spectrum_2dir(R, 0.005, 0.01), ref) < 1e-12
