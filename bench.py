@@ -728,11 +728,16 @@ def main(argv=None):
         nbytes = 1 << 30
         src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
-        for _ in range(3):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record()
+        for i in range(3):  # on torch's current stream, which its events see
             pk.stream_copy(dst, src, nbytes)
+            ev[i + 1].record()
         torch.cuda.synchronize()
+        copy_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(3)]
         print(json.dumps({"mode": "kernels", "workload": args.workload, "rk4_steps": args.rk4_steps,
                           "values_per_state": S, "copy_bytes": nbytes, "copies": 3,
+                          "copy_ms": copy_ms, "copy_GBps": 2 * nbytes / (min(copy_ms) * 1e-3) / 1e9,
                           "kernel_bytes": {k: v[2] for k, v in kt.items() if v[0] > 0},
                           "kernel_ms": {k: v[1] for k, v in kt.items() if v[0] > 0}}), flush=True)
         solver.close()

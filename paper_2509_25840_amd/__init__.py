@@ -316,8 +316,11 @@ def spectrum_2dir(R, tau1: float, tau3: float, stream=None):
 
 
 class Solver:
-    """One solver context: workspace allocated by torch on ``device``,
-    work issued on the current torch stream of that device."""
+    """One solver context: workspace allocated by torch on ``device``, work
+    issued on a stream of its own (default priority; a non-null stream lets
+    the library capture 2D-response waves as HIP graphs).  Calls that return
+    host data synchronize that stream; other work on the device can be
+    ordered after it with torch.cuda.synchronize() or solver.stream."""
 
     def __init__(self, params: Params, device: str = "cuda:0"):
         import torch
@@ -332,7 +335,10 @@ class Solver:
             raise ChfpeError(rc, L.chfpe_last_error(None).decode())
         with torch.cuda.device(self.device):
             self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
-            self.stream = torch.cuda.current_stream(self.device)
+            self.stream = torch.cuda.Stream(self.device)
+            # the workspace may be memory that pending work on the current
+            # stream still uses: start after it
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
         base = self._ws.data_ptr()
         aligned = (base + 255) // 256 * 256
         self._ctx = ctypes.c_void_p()
@@ -365,6 +371,7 @@ class Solver:
 
     def close(self):
         if getattr(self, "_ctx", None):
+            self.stream.synchronize()  # the workspace returns to torch's allocator
             lib().chfpe_destroy(self._ctx)
             self._ctx = None
             self._ws = None

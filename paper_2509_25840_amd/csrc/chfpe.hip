@@ -585,11 +585,11 @@ void plan_one(chfpe_ctx *c, int a, int run, std::vector<int> rest, QPass &out, i
   nmax = nmax_bucket(axis_len(c->d, a));
 }
 
-// LDS of a k_pcube workgroup: two fields of one round's (p_2, p_3) planes,
-// one pad value per p_3 row.
+// LDS of a k_pcube workgroup: a copy of the task's p block, and two fields
+// of one round's (p_2, p_3) planes with one pad value per p_3 row.
 size_t pcube_lds_bytes(const Derived &d, size_t tsize) {
   const int pl = pcube_planes(nmax_bucket(d.Np[0]));
-  return 2 * (size_t)pl * d.Np[1] * (d.Np[2] + 1) * tsize;
+  return ((size_t)d.P + 2 * (size_t)pl * d.Np[1] * (d.Np[2] + 1)) * tsize;
 }
 
 // Three modes take k_pcube when its register lines (p_1, at most 32 points)

@@ -615,12 +615,17 @@ k_pblock(const Geom g, const Tabs tb, const PBlock pb, const T *__restrict__ X, 
 // and the pointwise terms (as in k_pblock) are formed as the values arrive,
 // and one launch covers D_{p_1}, D_{p_2} and D_{p_3} of every element: the
 // q passes that follow read only h_n itself.
-// Thread (j2, j3) of the (p_2, p_3) plane keeps its p_1 line in registers:
-// acc (pointwise terms plus the solved p_2 and p_3 fields) and g1 (the
-// p_1 field, solved in place at the end).  Planes of constant p_1 go through
-// LDS in rounds of PL planes; G_{n,2} and G_{n,3} of a round
-// are solved along p_2 and p_3 there (two lanes per line when SPLIT: all
-// three axes have NB1 points), then added to acc.
+// Thread (j2, j3) of the (p_2, p_3) plane owns the p_1 line through it.
+//   Phase A streams h_n and its two p_1 neighbours over every plane with no
+//   barrier: the p_1 field and the p_1 and damping terms go to registers
+//   (acc, g1), h_n to an LDS copy of the block; the p_1 lines are then
+//   solved in registers and added to acc.
+//   Phase B takes the planes in rounds of PL: h_n from the thread's own LDS
+//   copy and the p_2, p_3 neighbours from memory (loads of round r + 1 are
+//   issued before round r's LDS work) give the p_2, p_3 terms and fields;
+//   the fields are solved along p_2 and p_3 in LDS planes (two lanes per
+//   line when SPLIT: all three axes have NB1 points) and added to acc.
+// Every neighbour read is skipped for a neighbour the task's element lacks.
 // PERTURB: out = X^x h as in k_pblock, with fields dX/dq_s h_n.
 struct PCube {
   int N1, N2, N3;  // p-axis lengths
@@ -629,28 +634,31 @@ struct PCube {
 };
 
 // Largest workgroup of k_pcube for a p_1 bucket: acc and g1 take
-// 2 NB1 values per thread, a round's loads 7 PL more, and every wave of the
-// workgroup must fit the register file together (512 VGPRs per SIMD lane).
+// 2 NB1 values per thread in phase A, acc and two rounds of loads in
+// phase B, and every wave of the workgroup must fit the register file
+// together (512 VGPRs per SIMD lane).
 template <typename T, int NB1>
 constexpr int pcube_max_threads() {
   return sizeof(T) == 8 ? (NB1 == 24 ? 768 : 512) : (NB1 >= 32 ? 768 : 1024);
 }
 
-// (p_2, p_3) planes per LDS round of k_pcube.
-constexpr int pcube_planes(const int nb1) { return nb1 == 24 ? 4 : nb1 / 4; }
+// (p_2, p_3) planes per LDS round of k_pcube (the block copy takes the
+// rest of the LDS).
+constexpr int pcube_planes(const int nb1) { return nb1 >= 32 ? 2 : nb1 == 24 ? 4 : nb1 / 4; }
 
 template <typename T, typename TO, int NB1, bool SPLIT, bool PERTURB, bool CLOS = false>
 __global__ void __launch_bounds__((pcube_max_threads<T, NB1>()))
 k_pcube(const Geom g, const Tabs tb, const PCube pc, const T *__restrict__ X, TO *__restrict__ out,
         const double *__restrict__ grad) {
-  constexpr int PL = pcube_planes(NB1);  // planes per round
+  constexpr int PL = pcube_planes(NB1);     // planes per round
   constexpr int NR = (NB1 + PL - 1) / PL;  // rounds
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int task = xcd_task(blockIdx.x, pc.nblk);
   if (task >= pc.ntasks) return;
   const int N1 = pc.N1, N2 = pc.N2, N3 = pc.N3, plane = pc.plane;
-  const int rs = N3 + 1;                  // LDS row stride (one pad value per p_3 row)
-  T *G2 = reinterpret_cast<T *>(smem_raw);  // [PL][N2][N3 + 1]
+  const int rs = N3 + 1;                      // LDS row stride (one pad value per p_3 row)
+  T *H = reinterpret_cast<T *>(smem_raw);     // [N1][plane] copy of h_n
+  T *G2 = H + N1 * plane;                     // [PL][N2][N3 + 1]
   T *G3 = G2 + PL * N2 * rs;
   const int ne_all = g.ne * g.nbatch;
   const int ea = task % ne_all;  // (branch, element): elements of one q point are adjacent tasks
@@ -669,12 +677,15 @@ k_pcube(const Geom g, const Tabs tb, const PCube pc, const T *__restrict__ X, TO
   const T *Xb = X + (long long)br * g.ne * g.E;
   const T *Xu[3];
   const T *Xd[3];
+  bool hu_[3], hd_[3];  // the element has n + e_s, n - e_s (uniform)
   T Fv[3], vu[3], vd[3], pwu[3], pwd[3];
   const double p2 = tb.pg[1 * kTab + j2], p3 = tb.pg[2 * kTab + j3];
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
     const int up = PERTURB ? -1 : tb.up[e * 3 + s];
     const int dn = PERTURB ? -1 : tb.dn[e * 3 + s];
+    hu_[s] = up >= 0;
+    hd_[s] = dn >= 0;
     Xu[s] = up >= 0 ? Xb + (long long)up * g.E + blk : Xe;
     Xd[s] = dn >= 0 ? Xb + (long long)dn * g.E + blk : Xe;
     if (PERTURB) {
@@ -695,67 +706,74 @@ k_pcube(const Geom g, const Tabs tb, const PCube pc, const T *__restrict__ X, TO
   const T c23 = PERTURB ? T(double(Fv[1]) * g.bm[1] * p2 + double(Fv[2]) * g.bm[2] * p3) : T(0);
   const T c1 = PERTURB ? T(double(Fv[0]) * g.bm[0]) : T(0);
   const T q2u = T(p2) * pwu[1], q2d = T(p2) * pwd[1], q3u = T(p3) * pwu[2], q3d = T(p3) * pwd[2];
+  const uint32_t own_off = (uint32_t)(own ? tid : 0);
 
+  // ---- phase A: h_n and its p_1 neighbours over every plane
   T acc[NB1], g1[NB1];
 #pragma unroll
   for (int i = 0; i < NB1; ++i) {
     acc[i] = T(0);
     g1[i] = T(0);
+    if (i < N1) {
+      const uint32_t o = (uint32_t)(i * plane) + own_off;
+      const T h = at_u32(Xe, o);
+      const T p1 = T(tb.pg[0 * kTab + i]);
+      if (PERTURB) {
+        acc[i] = -(c23 + c1 * p1) * h;
+        g1[i] = Fv[0] * h;
+      } else {
+        const T hu = hu_[0] ? at_u32(Xu[0], o) : T(0);
+        const T hd = hd_[0] ? at_u32(Xd[0], o) : T(0);
+        // n_1 zeta_1 gamma_1 V_1' p_1/2 h_{n-e_1} - V_1' beta p_1/(2 m_1) h_{n+e_1} - sum n gamma h_n
+        acc[i] = -dmp * h + p1 * (pwd[0] * hd - pwu[0] * hu);
+        g1[i] = Fv[0] * h + vu[0] * hu + vd[0] * hd;
+      }
+      if (own) H[i * plane + tid] = h;
+    }
   }
+  compact_inplace<T, NB1, CLOS>(g1, N1, T(g.dp_ca[0]), T(g.dp_cb[0]),
+                                CLOS ? tb.clos + 3 * 2 * kClosRows * kTab : nullptr);
+#pragma unroll
+  for (int i = 0; i < NB1; ++i) acc[i] += g1[i];
 
+  // ---- phase B: the p_2 and p_3 terms in rounds of PL planes
+  const double *ct2 = CLOS ? tb.clos + (3 + 1) * 2 * kClosRows * kTab : nullptr;
+  const double *ct3 = CLOS ? tb.clos + (3 + 2) * 2 * kClosRows * kTab : nullptr;
+  // round loads: the p_2 and p_3 neighbours of PL planes (planes past the
+  // block re-read its last plane: in bounds, unused)
+  auto load_round = [&](const int r, T (&u2)[PL], T (&d2)[PL], T (&u3)[PL], T (&d3)[PL]) {
+#pragma unroll
+    for (int k = 0; k < PL; ++k) {
+      const uint32_t o = (uint32_t)(min(r * PL + k, N1 - 1) * plane) + own_off;
+      u2[k] = (!PERTURB && hu_[1]) ? at_u32(Xu[1], o) : T(0);
+      d2[k] = (!PERTURB && hd_[1]) ? at_u32(Xd[1], o) : T(0);
+      u3[k] = (!PERTURB && hu_[2]) ? at_u32(Xu[2], o) : T(0);
+      d3[k] = (!PERTURB && hd_[2]) ? at_u32(Xd[2], o) : T(0);
+    }
+  };
+  T cu2[PL], cd2[PL], cu3[PL], cd3[PL];
+  load_round(0, cu2, cd2, cu3, cd3);
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const int i0 = r * PL;
     if (i0 >= N1) break;  // uniform
-    // ---- loads and pointwise terms of this round's planes
-    T h[PL], hu[3][PL], hd[3][PL];
+    T xu2[PL], xd2[PL], xu3[PL], xd3[PL];  // next round, in flight during this one
+    if (r + 1 < NR) load_round(r + 1, xu2, xd2, xu3, xd3);
 #pragma unroll
     for (int k = 0; k < PL; ++k) {
       const int i = i0 + k;
-      const uint32_t o = (uint32_t)(min(i, N1 - 1) * plane + (own ? tid : 0));
-      h[k] = at_u32(Xe, o);
-      if (!PERTURB) {
-#pragma unroll
-        for (int s = 0; s < 3; ++s) {
-          hu[s][k] = at_u32(Xu[s], o);
-          hd[s][k] = at_u32(Xd[s], o);
-        }
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < PL; ++k) {
-      const int i = i0 + k;
-      if (i < N1) {
-        const T p1 = T(tb.pg[0 * kTab + i]);
-        T a, f1, f2, f3;
-        if (PERTURB) {
-          a = -(c23 + c1 * p1) * h[k];
-          f1 = Fv[0] * h[k];
-          f2 = Fv[1] * h[k];
-          f3 = Fv[2] * h[k];
-        } else {
-          // n_s zeta_s gamma_s V_s' p_s/2 h_{n-e_s} - V_s' beta p_s/(2 m_s) h_{n+e_s} - sum n gamma h_n
-          a = -dmp * h[k] + p1 * (pwd[0] * hd[0][k] - pwu[0] * hu[0][k]) + q2d * hd[1][k] - q2u * hu[1][k] +
-              q3d * hd[2][k] - q3u * hu[2][k];
-          f1 = Fv[0] * h[k] + vu[0] * hu[0][k] + vd[0] * hd[0][k];
-          f2 = Fv[1] * h[k] + vu[1] * hu[1][k] + vd[1] * hd[1][k];
-          f3 = Fv[2] * h[k] + vu[2] * hu[2][k] + vd[2] * hd[2][k];
-        }
-        acc[i] = a;
-        g1[i] = f1;
-        if (own) {
-          const int li = (k * N2 + j2) * rs + j3;
-          G2[li] = f2;
-          G3[li] = f3;
-        }
+      if (i < N1 && own) {
+        const T h = H[i * plane + tid];
+        acc[i] += q2d * cd2[k] - q2u * cu2[k] + q3d * cd3[k] - q3u * cu3[k];
+        const int li = (k * N2 + j2) * rs + j3;
+        G2[li] = Fv[1] * h + vu[1] * cu2[k] + vd[1] * cd2[k];
+        G3[li] = Fv[2] * h + vu[2] * cu3[k] + vd[2] * cd3[k];
       }
     }
     __syncthreads();
-    // ---- p_2 lines of G2 (fixed k, j3) and p_3 lines of G3 (fixed k, j2)
+    // p_2 lines of G2 (fixed k, j3) and p_3 lines of G3 (fixed k, j2)
     const int npl = min(PL, N1 - i0);
     const int nl2 = npl * N3, nl = nl2 + npl * N2;
-    const double *ct2 = CLOS ? tb.clos + (3 + 1) * 2 * kClosRows * kTab : nullptr;
-    const double *ct3 = CLOS ? tb.clos + (3 + 2) * 2 * kClosRows * kTab : nullptr;
     if (SPLIT) {
       for (int hl = tid; hl < 2 * nl; hl += blockDim.x) {
         const int l = hl >> 1;
@@ -787,14 +805,20 @@ k_pcube(const Geom g, const Tabs tb, const PCube pc, const T *__restrict__ X, TO
       }
     }
     __syncthreads();  // the next round overwrites the planes
+    if (r + 1 < NR) {
+#pragma unroll
+      for (int k = 0; k < PL; ++k) {
+        cu2[k] = xu2[k];
+        cd2[k] = xd2[k];
+        cu3[k] = xu3[k];
+        cd3[k] = xd3[k];
+      }
+    }
   }
-  // ---- p_1 lines, one per thread, in registers
-  compact_inplace<T, NB1, CLOS>(g1, N1, T(g.dp_ca[0]), T(g.dp_cb[0]),
-                                CLOS ? tb.clos + 3 * 2 * kClosRows * kTab : nullptr);
   if (!own) return;
 #pragma unroll
   for (int i = 0; i < NB1; ++i)
-    if (i < N1) at_u32(Oe, (uint32_t)(i * plane + tid)) = TO(acc[i] + g1[i]);
+    if (i < N1) at_u32(Oe, (uint32_t)(i * plane + tid)) = TO(acc[i]);
 }
 
 // ---------------------------------------------------------------------------

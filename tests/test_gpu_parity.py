@@ -277,19 +277,30 @@ def test_response_2d_batched_fp64_parity(pk, name):
     assert np.array_equal(got, again)
 
 
-def test_graph_and_eager_waves_agree(pk, monkeypatch):
-    """The captured wave graph and the same launches issued directly give
-    identical results (deterministic kernels, fixed-order reductions)."""
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_graph_and_eager_waves_agree(pk, monkeypatch, prec):
+    """Waves captured as HIP graphs (the solver's own stream) and the same
+    launches issued directly give identical R (deterministic kernels,
+    fixed-order reductions).  The graph context replays its cached graphs in
+    three calls with eager work and synchronizations in between (a state
+    round trip, an observable); every replay must equal the eager result."""
     w = SMALL["m2_n12_k3"]
     A, B = _ops(2)
-    say("[graph vs eager]")
-    out = []
-    for flag in ("0", "1"):
-        monkeypatch.setenv("CHFPE_NO_GRAPH", flag)
-        with pk.Solver(pk.params_from_workload(w, precision=pk.CHFPE_FP64, batch=4)) as s:
-            s.equilibrate(5, 0.004)
-            out.append(s.response_2d(A, B, A, 9, 6, 1, 2, 0.004))
-    assert np.array_equal(out[0], out[1])
+    code = pk.CHFPE_FP64 if prec == "f64" else pk.CHFPE_FP32
+    say(f"[graph vs eager] {prec}")
+    monkeypatch.setenv("CHFPE_NO_GRAPH", "1")
+    with pk.Solver(pk.params_from_workload(w, precision=code, batch=4)) as s:
+        assert s.stream.cuda_stream != 0
+        s.equilibrate(5, 0.004)
+        eager = s.response_2d(A, B, A, 9, 6, 1, 2, 0.004)
+    monkeypatch.setenv("CHFPE_NO_GRAPH", "0")
+    with pk.Solver(pk.params_from_workload(w, precision=code, batch=4)) as s:
+        s.equilibrate(5, 0.004)
+        for rep in range(3):
+            got = s.response_2d(A, B, A, 9, 6, 1, 2, 0.004)
+            assert np.array_equal(got, eager), rep
+            s.set_state(s.get_state())
+            s.observe(A)
 
 
 @pytest.mark.parametrize("name", ["m2_n12_k3", "m3_n8_k2"])
