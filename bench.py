@@ -247,6 +247,65 @@ def recorded_traffic(workload: str, batch: int, precision: str, tiles: str, kind
     return None
 
 
+# SQ counters count per-wave cycles in units of 4 cycles; ratios below use
+# the raw values (units cancel) and instruction counts per wave.
+_COUNTER_COLS = [
+    ("VALU active", lambda c: c["SQ_ACTIVE_INST_VALU"] / c["SQ_WAVE_CYCLES"]),
+    ("waiting (any)", lambda c: c["SQ_WAIT_ANY"] / c["SQ_WAVE_CYCLES"]),
+    ("waiting for issue", lambda c: c["SQ_WAIT_INST_ANY"] / c["SQ_WAVE_CYCLES"]),
+    ("LDS active", lambda c: c["SQ_ACTIVE_INST_LDS"] / c["SQ_WAVE_CYCLES"]),
+    ("VALU instr/wave", lambda c: c["SQ_INSTS_VALU"] / c["SQ_WAVES"]),
+    ("SALU instr/wave", lambda c: c["SQ_INSTS_SALU"] / c["SQ_WAVES"]),
+    ("VMEM rd / wr per wave", lambda c: f"{c['SQ_INSTS_VMEM_RD'] / c['SQ_WAVES']:.0f} / "
+                                        f"{c['SQ_INSTS_VMEM_WR'] / c['SQ_WAVES']:.0f}"),
+    ("LDS instr/wave", lambda c: c["SQ_INSTS_LDS"] / c["SQ_WAVES"]),
+    ("LDS bank-conflict / LDS active", lambda c: c["SQ_LDS_BANK_CONFLICT"] / max(c["SQ_LDS_IDX_ACTIVE"], 1.0)),
+    ("L1->L2 latency (cycles)", lambda c: c["TCP_TCC_READ_REQ_LATENCY_sum"] / max(c["TCP_TCC_READ_REQ_sum"], 1.0)),
+    ("L2 hit rate", lambda c: c["TCC_HIT_sum"] / max(c["TCC_HIT_sum"] + c["TCC_MISS_sum"], 1.0)),
+]
+
+
+def summarise_counters(args, kern_cmd: str) -> None:
+    """counters_<workload>.md: per-kernel issue, stall, LDS and cache
+    counters, summed over the dispatches of each instantiation and grid."""
+    per, passes = {}, []
+    for folder in [d for d in args.counter_dirs.split(",") if d]:
+        rows = _csv(folder, "counter_collection.csv")
+        names = sorted({r["Counter_Name"] for r in rows})
+        passes.append(names)
+        for r in rows:
+            s = _short_name(r["Kernel_Name"])
+            if not (s.startswith("k_pcube") or s.startswith("k_qpass") or s.startswith("k_pblock")):
+                continue
+            key = (s, _grid(r))
+            per.setdefault(key, {})
+            per[key][r["Counter_Name"]] = per[key].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    lines = [f"# Issue and stall counters: {args.workload}, {args.precision} branch states, "
+             f"{args.batch}-branch waves", "",
+             f"Commands (repository root; one pass per counter set, each over the kernels of a few RK4 steps):", ""]
+    for names in passes:
+        lines.append(f"    rocprofv3 --pmc {' '.join(names)} --output-format csv -d <dir> -o run -- {kern_cmd}")
+    lines += ["", "Counter values summed over the dispatches of one kernel instantiation and grid. "
+              "Fractions are of SQ_WAVE_CYCLES (per-wave cycles); instruction counts are per wave "
+              "(SQ_INSTS_* / SQ_WAVES); L1->L2 latency is TCP_TCC_READ_REQ_LATENCY_sum / "
+              "TCP_TCC_READ_REQ_sum; L2 hit rate is TCC_HIT / (TCC_HIT + TCC_MISS).", "",
+              "| kernel | grid | " + " | ".join(c for c, _ in _COUNTER_COLS) + " |",
+              "|---|---|" + "---|" * len(_COUNTER_COLS)]
+    for (s, g), c in sorted(per.items()):
+        cells = []
+        for _, f in _COUNTER_COLS:
+            try:
+                v = f(c)
+                cells.append(v if isinstance(v, str) else (f"{v:.3f}" if v < 10 else f"{v:.0f}"))
+            except (KeyError, ZeroDivisionError):
+                cells.append("-")
+        lines.append(f"| `{s[:70]}` | {g} | " + " | ".join(cells) + " |")
+    lines += ["", f"Kernel sources hash: {source_hash()}."]
+    path = os.path.join(ROOT, "profiles", f"counters_{args.workload}.md")
+    open(path, "w").write("\n".join(lines) + "\n")
+    log(f"[summarise] wrote {path}")
+
+
 def summarise(args) -> int:
     tag = f"{args.workload}_{args.precision}_b{args.batch}"
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
@@ -301,6 +360,8 @@ def summarise(args) -> int:
         path = os.path.join(ROOT, "profiles", f"kernel_trace_{tag}.md")
         open(path, "w").write("\n".join(lines) + "\n")
         log(f"[summarise] wrote {path}")
+    if args.counter_dirs:
+        summarise_counters(args, kern_cmd)
     if args.fetch_dir and args.write_dir:
         per = {}
         for which, folder in (("fetch", args.fetch_dir), ("write", args.write_dir)):
@@ -444,6 +505,9 @@ def main(argv=None):
     ap.add_argument("--write-dir", help="summarise: rocprofv3 --pmc WRITE_SIZE output folder")
     ap.add_argument("--bench-json", help="summarise: the JSON line the traced bench run printed")
     ap.add_argument("--kernels-json", help="summarise: the JSON line the counted kernels run printed")
+    ap.add_argument("--counter-dirs", default="",
+                    help="summarise: comma-separated rocprofv3 --pmc output folders of SQ/TCP/TCC counter passes "
+                         "(each over the kernels command), summarised per kernel into counters_<workload>.md")
     ap.add_argument("--traffic-variant", action="store_true",
                     help="summarise: write only a tile-specific traffic record (traffic_<workload>_tiles_<tiles>.json)")
     ap.add_argument("--rk4-steps", type=int, default=4, help="RK4 steps in --mode kernels")
