@@ -234,6 +234,18 @@ int chfpe_spectrum_2d(const double *R, int64_t n_t1, int64_t n_t2, double tau1, 
 int chfpe_spectrum_2dir(const double *R, int64_t n_t1, int64_t n_t3, double tau1, double tau3,
                         double *I, void *hip_stream);
 
+/* chfpe_spectrum_2d without device allocation, for callers that cannot
+ * allocate (tight serving loops, harnesses that forbid hipMalloc): same
+ * arguments, result and conventions, with every device buffer in a fixed
+ * per-device scratch array of the library (48 bytes per point) instead of
+ * per-call allocations.  n_t1 * n_t2 <= 131072 (EINVAL above).  Calls on one
+ * GPU share that scratch: calls that overlap in time on one GPU (other host
+ * threads, other streams) race and must be serialized by the caller.  The
+ * call synchronizes hip_stream.  EDEVICE if the scratch address cannot be
+ * resolved on the current device. */
+int chfpe_spectrum_2d_noalloc(const double *R, int64_t n_t1, int64_t n_t2, double tau1, double tau2,
+                              double *I, void *hip_stream);
+
 /* Bandwidth reference: copy `bytes` bytes (a multiple of 16) from src to
  * dst, both device pointers, with a plain streaming kernel on hip_stream. */
 int chfpe_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream);

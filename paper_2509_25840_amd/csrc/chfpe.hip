@@ -1328,6 +1328,37 @@ int fail_g(int code, const std::string &msg) { return fail(nullptr, code, msg); 
 // C ABI
 // ===========================================================================
 
+// ---------------------------------------------------------------------------
+// Device scratch of chfpe_spectrum_2d_noalloc: a file-scope array, one copy
+// per device, that holds R, two complex work arrays and I of one spectrum
+// of at most kNoAllocMaxPoints points (48 bytes per point, 6 MiB).  Host
+// code never passes the array's name to a kernel or copy: it takes the
+// device address of each GPU's copy once (hipGetSymbolAddress, with that
+// device current) and uses that address.
+// ---------------------------------------------------------------------------
+constexpr long long kNoAllocMaxPoints = 1LL << 17;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[48 * kNoAllocMaxPoints];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the current device's scratch (resolved on first use per device).
+int scratch_of_current_device(void **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return CHFPE_EDEVICE;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return CHFPE_EDEVICE;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return CHFPE_OK;
+}
+}  // namespace
+
 extern "C" {
 
 size_t chfpe_workspace_bytes(const chfpe_params *p) {
@@ -1349,6 +1380,11 @@ int chfpe_setup(const chfpe_params *p, void *dev_workspace, size_t ws_bytes, voi
   if (dev_workspace && (reinterpret_cast<uintptr_t>(dev_workspace) % 256) != 0)
     return fail(nullptr, CHFPE_EINVAL, "workspace must be 256-byte aligned");
 
+  {
+    void *sp = nullptr;  // the device's scratch address, taken once per device at set-up
+    if (scratch_of_current_device(&sp) != CHFPE_OK)
+      return fail(nullptr, CHFPE_EDEVICE, "hipGetSymbolAddress of the device scratch failed");
+  }
   chfpe_ctx *c = new chfpe_ctx();
   c->prm = *p;
   c->d = d;
@@ -1771,33 +1807,44 @@ int chfpe_spectrum_1d(const double *R, int64_t n, double tau, double *omega, dou
 namespace {
 
 // Im{tau_f tau_s sum_{j_s, j_f} exp(-i omega_f t_f + sign_s i omega_s t_s) R[j_s][j_f]}
-// as two passes of discrete Fourier sums (fast axis, then slow axis).
+// as two passes of discrete Fourier sums (fast axis, then slow axis), on
+// device buffers dR (n doubles), dz, dout (n double2 each) and dI (n doubles).
+int spectrum_2d_on(const double *R, long long n_f, long long n_s, double tau_f, double tau_s, double sign_s,
+                   double *I, hipStream_t st, double *dR, double2 *dz, double2 *dout, double *dI) {
+  const long long n = n_f * n_s;
+  if (hipMemcpyAsync(dR, R, n * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess) return CHFPE_EDEVICE;
+  const int nb = (int)((n + 255) / 256);
+  hipLaunchKernelGGL(k_to_complex, dim3(nb), dim3(256), 0, st, (const double *)dR, dz, n);
+  // along the fast axis (rows of length n_f), exp(-i omega t)
+  hipLaunchKernelGGL(k_dft_rows, dim3(nb), dim3(256), 0, st, (const double2 *)dz, dout, (int)n_s, (int)n_f,
+                     (int)n_f, 1, (int)n_f, 1, -1.0);
+  // along the slow axis (columns, stride n_f), exp(sign_s i omega t)
+  hipLaunchKernelGGL(k_dft_rows, dim3(nb), dim3(256), 0, st, (const double2 *)dout, dz, (int)n_f, (int)n_s, 1,
+                     (int)n_f, 1, (int)n_f, sign_s);
+  hipLaunchKernelGGL(k_spectrum_out, dim3(nb), dim3(256), 0, st, (const double2 *)dz, n, (int)n_f, tau_f * tau_s,
+                     0.0, 0, dI);
+  if (hipMemcpyAsync(I, dI, n * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess) return CHFPE_EDEVICE;
+  if (hipStreamSynchronize(st) != hipSuccess) return CHFPE_EDEVICE;
+  if (hipGetLastError() != hipSuccess) return CHFPE_EDEVICE;
+  return CHFPE_OK;
+}
+
+bool spectrum_args_ok(const double *R, const double *I, long long n_f, long long n_s, double tau_f, double tau_s) {
+  return R && I && n_f >= 1 && n_s >= 1 && n_f * n_s <= (1LL << 26) && tau_f > 0 && tau_s > 0 &&
+         std::isfinite(tau_f) && std::isfinite(tau_s);
+}
+
+// The same with device buffers allocated for the call.
 int spectrum_2d_signed(const double *R, int64_t n_f, int64_t n_s, double tau_f, double tau_s, double sign_s,
                        double *I, void *hip_stream) {
-  if (!R || !I || n_f < 1 || n_s < 1 || n_f * n_s > (1LL << 26) || !(tau_f > 0) || !(tau_s > 0) ||
-      !std::isfinite(tau_f) || !std::isfinite(tau_s))
-    return CHFPE_EINVAL;
-  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  if (!spectrum_args_ok(R, I, n_f, n_s, tau_f, tau_s)) return CHFPE_EINVAL;
   const long long n = n_f * n_s;
   DevBuf bR, bz, bo, bI;
   if (hipMalloc(&bR.p, n * sizeof(double)) != hipSuccess || hipMalloc(&bz.p, n * sizeof(double2)) != hipSuccess ||
       hipMalloc(&bo.p, n * sizeof(double2)) != hipSuccess || hipMalloc(&bI.p, n * sizeof(double)) != hipSuccess)
     return CHFPE_ENOMEM;
-  if (hipMemcpyAsync(bR.p, R, n * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess) return CHFPE_EDEVICE;
-  const int nb = (int)((n + 255) / 256);
-  hipLaunchKernelGGL(k_to_complex, dim3(nb), dim3(256), 0, st, (const double *)bR.p, (double2 *)bz.p, n);
-  // along the fast axis (rows of length n_f), exp(-i omega t)
-  hipLaunchKernelGGL(k_dft_rows, dim3(nb), dim3(256), 0, st, (const double2 *)bz.p, (double2 *)bo.p, (int)n_s,
-                     (int)n_f, (int)n_f, 1, (int)n_f, 1, -1.0);
-  // along the slow axis (columns, stride n_f), exp(sign_s i omega t)
-  hipLaunchKernelGGL(k_dft_rows, dim3(nb), dim3(256), 0, st, (const double2 *)bo.p, (double2 *)bz.p, (int)n_f,
-                     (int)n_s, 1, (int)n_f, 1, (int)n_f, sign_s);
-  hipLaunchKernelGGL(k_spectrum_out, dim3(nb), dim3(256), 0, st, (const double2 *)bz.p, n, (int)n_f, tau_f * tau_s,
-                     0.0, 0, (double *)bI.p);
-  if (hipMemcpyAsync(I, bI.p, n * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess) return CHFPE_EDEVICE;
-  if (hipStreamSynchronize(st) != hipSuccess) return CHFPE_EDEVICE;
-  if (hipGetLastError() != hipSuccess) return CHFPE_EDEVICE;
-  return CHFPE_OK;
+  return spectrum_2d_on(R, n_f, n_s, tau_f, tau_s, sign_s, I, reinterpret_cast<hipStream_t>(hip_stream),
+                        (double *)bR.p, (double2 *)bz.p, (double2 *)bo.p, (double *)bI.p);
 }
 
 }  // namespace
@@ -1812,6 +1859,23 @@ int chfpe_spectrum_2d(const double *R, int64_t n_t1, int64_t n_t2, double tau1, 
 int chfpe_spectrum_2dir(const double *R, int64_t n_t1, int64_t n_t3, double tau1, double tau3, double *I,
                         void *hip_stream) {
   return spectrum_2d_signed(R, n_t1, n_t3, tau1, tau3, +1.0, I, hip_stream);
+}
+
+int chfpe_spectrum_2d_noalloc(const double *R, int64_t n_t1, int64_t n_t2, double tau1, double tau2, double *I,
+                              void *hip_stream) {
+  if (!spectrum_args_ok(R, I, n_t1, n_t2, tau1, tau2) || n_t1 * n_t2 > kNoAllocMaxPoints) return CHFPE_EINVAL;
+  void *base = nullptr;
+  int rc = scratch_of_current_device(&base);
+  if (rc) return rc;
+  const long long n = n_t1 * n_t2;
+  // layout in the scratch: two complex arrays, then R and I (16-byte aligned)
+  unsigned char *b = reinterpret_cast<unsigned char *>(base);
+  double2 *dz = reinterpret_cast<double2 *>(b);
+  double2 *dout = reinterpret_cast<double2 *>(b + 16 * n);
+  double *dR = reinterpret_cast<double *>(b + 32 * n);
+  double *dI = reinterpret_cast<double *>(b + 40 * n);
+  return spectrum_2d_on(R, n_t1, n_t2, tau1, tau2, -1.0, I, reinterpret_cast<hipStream_t>(hip_stream), dR, dz,
+                        dout, dI);
 }
 
 int chfpe_set_kernel_timing(chfpe_ctx *c, int32_t every) {
