@@ -420,7 +420,8 @@ def summarise(args) -> int:
                   "| kind | launches | fetch MB | write MB | total MB | algorithmic MB | total / algorithmic |",
                   "|---|---|---|---|---|---|---|"]
         for kind in rec["bytes_per_launch"]:
-            a = alg.get(kind)
+            # the two middle RK4 stages share one instantiation (qpass_rk4_s23)
+            a = alg.get(kind) or (alg.get("qpass_rk4_s2") if kind == "qpass_rk4_s23" else None)
             t = rec["bytes_per_launch"][kind]
             lines.append(f"| {kind} | {per[kind]['fetch'][0]} | {rec['fetch_bytes_per_launch'][kind] / 1e6:.2f} | "
                          f"{rec['write_bytes_per_launch'][kind] / 1e6:.2f} | {t / 1e6:.2f} | "
