@@ -70,8 +70,8 @@ enum { CHFPE_FP64 = 0, CHFPE_FP32 = 1 };
  *     with batch > 1 or CHFPE_FP32, branches run in waves of `batch` states
  *     (batch x 4 extra state buffers of the branch type in the workspace),
  *     each wave's t2 loop as one captured HIP graph.
- * Limits: 1 <= M <= 3, 0 <= K <= 12, 5 <= N <= 48 on every axis (the last
- * two p axes also within the tiling limit under chfpe_setup), all
+ * Limits: 1 <= M <= 3, 0 <= K <= 12, 5 <= N <= 48 on every axis (the p
+ * axes also within the tiling limit under chfpe_setup), all
  * masses, beta, L > 0, one element below 2^29 points, and
  * exp(-beta H_sys/2) representable (> 1e-150) everywhere on the grid.
  */
@@ -125,11 +125,16 @@ size_t chfpe_workspace_bytes(const chfpe_params *p);
  * see below, or a batch so large that one launch over all its states would
  * exceed a dispatch's 2^32 work-items), ENOMEM (workspace too small or
  * allocation failed), EDEVICE.
- * Tiling limit (M >= 2): the last two p axes, N_{M-1} x N_M points, are one
- * LDS tile with N_M threads per row group; N_{M-1} needs a divisor d with
- * d * N_M <= 256 and N_{M-1} <= 4 d.  Every size up to 16 qualifies, and so
- * do equal pairs of 18, 20-22, 24, 27, 28 and 32; 17, 19, 23, 25, 26, 29-31
- * and above 32 do not.  chfpe_workspace_bytes returns 0 for them. */
+ * Tiling limit (M >= 2): the p block of every q point must fit one of two
+ * tiles.  (a) The last two p axes, N_{M-1} x N_M points, as one LDS tile with
+ * N_M threads per row group: N_{M-1} needs a divisor d with d * N_M <= 256 and
+ * N_{M-1} <= 4 d (every size up to 16, and equal pairs of 18, 20-22, 24, 27,
+ * 28 and 32).  (b) The whole block in one workgroup of one thread per
+ * (p_2, p_3) point (two modes: per p_2 point) holding a p_1 line of at most 32
+ * points (three modes) or 48 (two modes), with at most 512-768 threads and
+ * the block in 160 KB of LDS.  Three modes take (b) wherever it fits, two
+ * modes where (a) does not.  chfpe_workspace_bytes returns 0 when neither
+ * fits. */
 int chfpe_setup(const chfpe_params *p, void *dev_workspace, size_t ws_bytes, void *hip_stream,
                 chfpe_ctx **out);
 
@@ -292,8 +297,9 @@ int chfpe_autotune(chfpe_ctx *ctx, int32_t n_steps);
  * CHFPE_TUNE_PB_NB, CHFPE_TUNE_PB_SPLIT and CHFPE_TUNE_Q_PC environment
  * variables reproduce; out[9] the k_pblock task order (consecutive block
  * groups of one state before the next element) and out[10] its request
- * (0 = 1; CHFPE_TUNE_PB_RUN).  Writes min(n, 11) values and returns that
- * count. */
+ * (0 = 1; CHFPE_TUNE_PB_RUN); out[11] 1 when one workgroup per q point takes
+ * the whole p block (k_pcube; out[0], out[9] then describe no launch).
+ * Writes min(n, 12) values and returns that count. */
 int chfpe_tile_config(const chfpe_ctx *ctx, int32_t *out, int32_t n);
 
 /* ---- Learned per-axis closure (coarse grids) -------------------------------

@@ -72,9 +72,9 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 struct Derived {
   int prec = 0, B = 1;    // precision of branch states; branches per wave
   bool batched = false;   // 2D responses use the batched branch buffers
-  int M, K, ne;
-  int Nq[3], Np[3];
-  int Q, P;
+  int M = 0, K = 0, ne = 0;
+  int Nq[3] = {0, 0, 0}, Np[3] = {0, 0, 0};  // axes s >= M stay 0
+  int Q = 0, P = 0;
   long long E, S;  // points per element, values per state
   std::vector<int> nvec;  // ne * M
 };
@@ -117,6 +117,28 @@ PBShape pblock_shape(const Derived &d) {
   s.nb_lo = 1;
   while (s.nb_lo < s.nb_hi && s.items(d, s.nb_lo) > kMaxGridItems) ++s.nb_lo;
   return s;
+}
+
+int nmax_bucket(int n) {
+  return n <= 8 ? 8 : n <= 12 ? 12 : n <= 16 ? 16 : n <= 24 ? 24 : n <= 32 ? 32 : 48;
+}
+
+// The p block of k_pcube for two or three modes: p_1 lines (registers) of
+// up to 32 points (three modes) or 48 (two modes), a (p_2, p_3) plane (two
+// modes: a p_2 row) of threads within the workgroup bound, and the LDS copy
+// of the block plus a round's planes within 160 KB (FP64).
+int pcube_n3(const Derived &d) { return d.M == 3 ? d.Np[2] : 1; }
+bool pcube_shape_ok(const Derived &d) {
+  if (d.M < 2) return false;
+  const int nb1 = nmax_bucket(d.Np[0]);
+  const int plane = d.Np[1] * pcube_n3(d);
+  const int maxthr = nb1 > 32 ? pcube_max_threads<double, 48>()
+                     : nb1 >= 32 ? pcube_max_threads<double, 32>()
+                     : nb1 >= 24 ? pcube_max_threads<double, 24>() : pcube_max_threads<double, 16>();
+  const size_t lds = ((size_t)d.P + 2 * (size_t)pcube_planes(nb1) * d.Np[1] * (pcube_n3(d) + 1)) * sizeof(double);
+  const long long items = ((long long)d.ne * d.Q * (d.batched ? d.B : 1) + 7) / 8 * 8 * ((plane + 63) / 64 * 64);
+  return nb1 <= (d.M == 3 ? 32 : 48) && (plane + 63) / 64 * 64 <= maxthr && lds <= 160 * 1024 &&
+         items <= 0xFFFFFFFFLL;
 }
 
 bool derive(const chfpe_params *p, Derived &d, std::string &err) {
@@ -210,11 +232,14 @@ bool derive(const chfpe_params *p, Derived &d, std::string &err) {
   }
   const PBShape ps = pblock_shape(d);
   if (ps.rows > kPBlockRPT * ps.RG) {
+    if (pcube_shape_ok(d)) return true;  // k_pcube takes the p block
     err = "the last two p axes (" + std::to_string(ps.rows) + " x " + std::to_string(ps.cols) +
-          " points) cannot be tiled: N_{M-1} needs a divisor d with d * N_M <= 256 and N_{M-1} <= 4 d";
+          " points) cannot be tiled: N_{M-1} needs a divisor d with d * N_M <= 256 and N_{M-1} <= 4 d, "
+          "and the p block does not fit one k_pcube workgroup";
     return false;
   }
   if (ps.items(d, ps.nb_lo) > kMaxGridItems) {
+    if (pcube_shape_ok(d)) return true;
     err = "batch too large: the p-block launch over every branch state exceeds one dispatch (2^32 work-items)";
     return false;
   }
@@ -309,9 +334,6 @@ std::vector<long long> tune_key(const Derived &d) {
   return k;
 }
 
-int nmax_bucket(int n) {
-  return n <= 8 ? 8 : n <= 12 ? 12 : n <= 16 ? 16 : n <= 24 ? 24 : n <= 32 ? 32 : 48;
-}
 
 }  // namespace
 
@@ -344,6 +366,7 @@ struct chfpe_ctx {
   int tune_q_pc = 0;    // run positions per two-axis k_qpass tile (0: automatic)
   int tune_pb_split = -1;  // k_pblock lines solved by lane pairs (-1: automatic)
   int tune_pb_run = 0;     // k_pblock consecutive block groups per state in task order (0: 1)
+  int tune_pc_pad = 0;     // k_pcube LDS plane row pad (0: 1)
   bool capturing = false;  // a HIP graph is being captured: no event timing
   bool closure_on = false; // right-hand sides use the closure stencil weights (tb.clos)
   bool use_graphs = true;
@@ -586,22 +609,21 @@ void plan_one(chfpe_ctx *c, int a, int run, std::vector<int> rest, QPass &out, i
 }
 
 // LDS of a k_pcube workgroup: a copy of the task's p block, and two fields
-// of one round's (p_2, p_3) planes with one pad value per p_3 row.
-size_t pcube_lds_bytes(const Derived &d, size_t tsize) {
+// of one round's (p_2, p_3) planes with rows of N_3 + pad values.
+size_t pcube_lds_bytes(const Derived &d, size_t tsize, int pad) {
   const int pl = pcube_planes(nmax_bucket(d.Np[0]));
-  return ((size_t)d.P + 2 * (size_t)pl * d.Np[1] * (d.Np[2] + 1)) * tsize;
+  return ((size_t)d.P + 2 * (size_t)pl * d.Np[1] * (size_t)(pcube_n3(d) + pad)) * tsize;
 }
 
-// Three modes take k_pcube when its register lines (p_1, at most 32 points)
-// and its (p_2, p_3) plane of threads fit one workgroup (FP64 bound).
-bool pcube_fits(const chfpe_ctx *c) {
+// Three modes take k_pcube wherever its block fits (CHFPE_PCUBE=0 keeps the
+// p-block path where that one tiles); two modes take it only for p blocks
+// the p-block tile cannot cover (p axes above 32 points).
+bool use_pcube(const chfpe_ctx *c) {
   const Derived &d = c->d;
-  if (d.M != 3 || !c->allow_pcube) return false;
-  const int nb1 = nmax_bucket(d.Np[0]);
-  const int plane = d.Np[1] * d.Np[2];
-  const int maxthr = nb1 >= 32 ? pcube_max_threads<double, 32>() : nb1 >= 24 ? pcube_max_threads<double, 24>()
-                                                                            : pcube_max_threads<double, 16>();
-  return nb1 <= 32 && (plane + 63) / 64 * 64 <= maxthr && pcube_lds_bytes(d, sizeof(double)) <= 160 * 1024;
+  if (!pcube_shape_ok(d)) return false;
+  const PBShape ps = pblock_shape(d);
+  const bool pblock_ok = ps.rows <= kPBlockRPT * ps.RG && ps.items(d, ps.nb_lo) <= kMaxGridItems;
+  return !pblock_ok || (d.M == 3 && c->allow_pcube);
 }
 
 // Choose tile shapes.  Returns false when a k_qpass launch over every state
@@ -653,34 +675,45 @@ bool plan(chfpe_ctx *c) {
     plan_one(c, 0, d.P, {}, ln.qf, ln.qf_threads, ln.qf_nmax);
     ln.qf_lds = 0;
     ln.has_qx = false;
-  } else if (M == 2) {
-    ln.has_qa = false;
-    ln.qf_two = true;
-    plan_two(c, 0, 1, d.P, {}, ln.qf, ln.qf_threads, ln.qf_lds, ln.qf_nmax);
-    ln.has_qx = false;
-  } else if (pcube_fits(c)) {
-    // all p axes per q point (k_pcube), then (q_2, q_3) over whole p-blocks,
-    // then q_1 alone (lines in registers) with the stage update
+  } else if (use_pcube(c)) {
+    // all p axes per q point (k_pcube); three modes then take (q_2, q_3)
+    // over whole p-blocks and q_1 alone (lines in registers) with the stage
+    // update, two modes (q_1, q_2)
     ln.pcube = true;
     PCube &pq = ln.pcb;
     pq.N1 = d.Np[0];
     pq.N2 = d.Np[1];
-    pq.N3 = d.Np[2];
+    pq.N3 = pcube_n3(d);
     pq.plane = pq.N2 * pq.N3;
     pq.ntasks = (int)std::min<long long>((long long)d.ne * d.Q, 1LL << 30);
     pq.nblk = pad8(pq.ntasks);
     ln.pcube_nb1 = nmax_bucket(pq.N1);
     ln.pcube_threads = (pq.plane + 63) / 64 * 64;
-    ln.pcube_lds = pcube_lds_bytes(d, sizeof(double));
+    // row pad of the LDS planes (CHFPE_TUNE_PC_PAD, 1..8), kept only while the LDS fits
+    pq.rs = pq.N3 + 1;
+    if (c->tune_pc_pad > 1 && pcube_lds_bytes(d, sizeof(double), c->tune_pc_pad) <= 160 * 1024)
+      pq.rs = pq.N3 + c->tune_pc_pad;
+    ln.pcube_lds = pcube_lds_bytes(d, sizeof(double), pq.rs - pq.N3);
     ln.pcube_split = pq.N1 == ln.pcube_nb1 && pq.N2 == pq.N1 && pq.N3 == pq.N1 && c->tune_pb_split != 0;
     pb.nb = 1;  // k_pblock is not launched: one shape for the autotuner
     pb.split = ln.pcube_split ? 1 : 0;
     pb.run = 1;
-    ln.has_qa = true;
-    plan_two(c, 1, 2, d.P, {0}, ln.qa, ln.qa_threads, ln.qa_lds, ln.qa_nmax);
-    ln.qf_two = false;
-    plan_one(c, 0, (d.Q / d.Nq[0]) * d.P, {}, ln.qf, ln.qf_threads, ln.qf_nmax);
-    ln.qf_lds = 0;
+    ln.has_qx = false;
+    if (M == 3) {
+      ln.has_qa = true;
+      plan_two(c, 1, 2, d.P, {0}, ln.qa, ln.qa_threads, ln.qa_lds, ln.qa_nmax);
+      ln.qf_two = false;
+      plan_one(c, 0, (d.Q / d.Nq[0]) * d.P, {}, ln.qf, ln.qf_threads, ln.qf_nmax);
+      ln.qf_lds = 0;
+    } else {
+      ln.has_qa = false;
+      ln.qf_two = true;
+      plan_two(c, 0, 1, d.P, {}, ln.qf, ln.qf_threads, ln.qf_lds, ln.qf_nmax);
+    }
+  } else if (M == 2) {
+    ln.has_qa = false;
+    ln.qf_two = true;
+    plan_two(c, 0, 1, d.P, {}, ln.qf, ln.qf_threads, ln.qf_lds, ln.qf_nmax);
     ln.has_qx = false;
   } else {
     // (q_2, q_3) over whole p-blocks, then (q_1, p_1) over (p_2, p_3) planes
@@ -852,7 +885,7 @@ void launch_pblock_t(chfpe_ctx *c, const Batch &b, const T *X, TO *out, const do
 template <typename T, typename TO, int NB1, bool SPLIT, bool PERTURB>
 void launch_pcube_s(chfpe_ctx *c, const Batch &b, const T *X, TO *out, const double *grad) {
   const Launch &ln = c->ln;
-  const size_t lds = pcube_lds_bytes(c->d, sizeof(T));
+  const size_t lds = pcube_lds_bytes(c->d, sizeof(T), b.pcb.rs - b.pcb.N3);
   if constexpr (kClosureBuilt<T, TO, NB1>) {
     if (c->closure_on) {
       auto kern = k_pcube<T, TO, NB1, SPLIT, PERTURB, true>;
@@ -883,7 +916,8 @@ void launch_pcube_t(chfpe_ctx *c, const Batch &b, const T *X, TO *out, const dou
     case 12: launch_pcube_n<T, TO, 12, PERTURB>(c, b, X, out, grad); break;
     case 16: launch_pcube_n<T, TO, 16, PERTURB>(c, b, X, out, grad); break;
     case 24: launch_pcube_n<T, TO, 24, PERTURB>(c, b, X, out, grad); break;
-    default: launch_pcube_n<T, TO, 32, PERTURB>(c, b, X, out, grad); break;
+    case 32: launch_pcube_n<T, TO, 32, PERTURB>(c, b, X, out, grad); break;
+    default: launch_pcube_n<T, TO, 48, PERTURB>(c, b, X, out, grad); break;
   }
 }
 
@@ -1441,6 +1475,7 @@ int chfpe_setup(const chfpe_params *p, void *dev_workspace, size_t ws_bytes, voi
   if (const char *v = std::getenv("CHFPE_TUNE_Q_PC")) c->tune_q_pc = std::atoi(v);
   if (const char *v = std::getenv("CHFPE_TUNE_PB_SPLIT")) c->tune_pb_split = std::atoi(v);
   if (const char *v = std::getenv("CHFPE_TUNE_PB_RUN")) c->tune_pb_run = std::atoi(v);
+  if (const char *v = std::getenv("CHFPE_TUNE_PC_PAD")) c->tune_pc_pad = std::max(0, std::min(8, std::atoi(v)));
   if (const char *v = std::getenv("CHFPE_NO_GRAPH")) c->use_graphs = std::atoi(v) == 0;
   if (const char *v = std::getenv("CHFPE_PCUBE")) c->allow_pcube = std::atoi(v) != 0;
   std::vector<double> F, Vp, pm, pg, sq, sp, wp, cc, tc, damp;
@@ -1954,10 +1989,11 @@ int chfpe_autotune(chfpe_ctx *c, int32_t n_steps) {
 
 int chfpe_tile_config(const chfpe_ctx *c, int32_t *out, int32_t n) {
   if (!c || !out || n < 0) return CHFPE_EINVAL;
-  const int32_t v[11] = {c->ln.pb.nb,  c->ln.pb.split,    c->ln.pb_threads,
+  const int32_t v[12] = {c->ln.pb.nb,  c->ln.pb.split,    c->ln.pb_threads,
                          c->ln.qf.pc,  c->ln.has_qa ? c->ln.qa.pc : 0, c->ln.qf_threads,
-                         c->tune_pb_nb, c->tune_pb_split, c->tune_q_pc, c->ln.pb.run, c->tune_pb_run};
-  const int k = n < 11 ? n : 11;
+                         c->tune_pb_nb, c->tune_pb_split, c->tune_q_pc, c->ln.pb.run, c->tune_pb_run,
+                         c->ln.pcube ? 1 : 0};
+  const int k = n < 12 ? n : 12;
   for (int i = 0; i < k; ++i) out[i] = v[i];
   return k;
 }

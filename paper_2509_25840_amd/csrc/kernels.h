@@ -282,6 +282,54 @@ __device__ __forceinline__ void compact_split(T *G, const int base, const int st
   }
 }
 
+// Same solve as compact_split with the half-line in registers: each lane
+// reads its N/2 values and the R values past the middle from LDS first (all
+// reads independent of each other), eliminates and back-substitutes in
+// registers, and writes its half at the end, so no LDS access sits in the
+// elimination chain.  The partner lane reads before either lane writes (the
+// writes depend on the exchanged value).  Both lanes of a pair must call this
+// together.
+template <typename T, int N, bool CLOS = false>
+__device__ __forceinline__ void compact_split_regs(T *G, const int base, const int stride, const int half, T ca,
+                                                   T cb, const double *ct = nullptr) {
+  static_assert(N % 2 == 0 && N >= 6, "split solve needs an even line of at least 6");
+  constexpr int H = N / 2;
+  constexpr int R = CLOS ? 3 : 2;  // stencil reach
+  constexpr int NL = H + R;
+  constexpr double cm = kThomas.cp[H - 1];
+  constexpr double inv1mc2 = 1.0 / (1.0 - cm * cm);
+  const int step = half ? -stride : stride;
+  const int start = base + (half ? (N - 1) * stride : 0);
+  if (half) {
+    ca = -ca;
+    cb = -cb;
+  }
+  const double *cto = CLOS ? ct + (half ? kClosRows * kTab : 0) : ct;
+  T f[NL];
+#pragma unroll
+  for (int j = 0; j < NL; ++j) f[j] = G[start + j * step];
+  T d[H];
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    const T fm1 = i >= 1 ? f[i >= 1 ? i - 1 : 0] : T(0);
+    const T fm2 = i >= 2 ? f[i >= 2 ? i - 2 : 0] : T(0);
+    const T fm3 = (CLOS && i >= 3) ? f[i >= 3 ? i - 3 : 0] : T(0);
+    const T fp3 = CLOS ? f[i + 3 < NL ? i + 3 : NL - 1] : T(0);
+    const T r = stencil_rhs<T, CLOS>(i, fm3, fm2, fm1, f[i + 1], f[i + 2], fp3, ca, cb, cto);
+    d[i] = i == 0 ? r : __builtin_fma(T(-kThomas.inv[i] / 3.0), d[i >= 1 ? i - 1 : 0], r * T(kThomas.inv[i]));
+  }
+  const T other = __shfl_xor(d[H - 1], 1);
+  T x = (d[H - 1] - T(cm) * other) * T(inv1mc2);
+  d[H - 1] = x;
+#pragma unroll
+  for (int i = H - 2; i >= 0; --i) {
+    x = d[i] - T(kThomas.cp[i]) * x;
+    d[i] = x;
+  }
+#pragma unroll
+  for (int i = 0; i < H; ++i) G[start + i * step] = d[i];
+}
+
 // Element idx of a workgroup-uniform base pointer.  The byte offset is formed
 // in 32 bits, so the access takes the scalar-base form (one 32-bit offset
 // register shared by every array indexed alike); callers keep idx * sizeof(T)
@@ -630,6 +678,7 @@ k_pblock(const Geom g, const Tabs tb, const PBlock pb, const T *__restrict__ X, 
 struct PCube {
   int N1, N2, N3;  // p-axis lengths
   int plane;       // N2 * N3: threads that own a p_1 line
+  int rs;          // LDS row stride of a plane field: N3 plus a pad
   int ntasks, nblk;
 };
 
@@ -639,11 +688,12 @@ struct PCube {
 // together (512 VGPRs per SIMD lane).
 template <typename T, int NB1>
 constexpr int pcube_max_threads() {
-  return sizeof(T) == 8 ? (NB1 == 24 ? 768 : 512) : (NB1 >= 32 ? 768 : 1024);
+  return NB1 > 32 ? 256 : sizeof(T) == 8 ? (NB1 == 24 ? 768 : 512) : (NB1 >= 32 ? 768 : 1024);
 }
 
 // (p_2, p_3) planes per LDS round of k_pcube (the block copy takes the
-// rest of the LDS).
+// rest of the LDS).  Two modes use the same kernel with a unit third axis:
+// the "planes" are p_2 rows and the p_3 fields vanish (zero tables).
 constexpr int pcube_planes(const int nb1) { return nb1 >= 32 ? 2 : nb1 == 24 ? 4 : nb1 / 4; }
 
 template <typename T, typename TO, int NB1, bool SPLIT, bool PERTURB, bool CLOS = false>
@@ -656,9 +706,9 @@ k_pcube(const Geom g, const Tabs tb, const PCube pc, const T *__restrict__ X, TO
   const int task = xcd_task(blockIdx.x, pc.nblk);
   if (task >= pc.ntasks) return;
   const int N1 = pc.N1, N2 = pc.N2, N3 = pc.N3, plane = pc.plane;
-  const int rs = N3 + 1;                      // LDS row stride (one pad value per p_3 row)
+  const int rs = pc.rs;                       // LDS row stride (p_3 row plus a pad)
   T *H = reinterpret_cast<T *>(smem_raw);     // [N1][plane] copy of h_n
-  T *G2 = H + N1 * plane;                     // [PL][N2][N3 + 1]
+  T *G2 = H + N1 * plane;                     // [PL][N2][rs]
   T *G3 = G2 + PL * N2 * rs;
   const int ne_all = g.ne * g.nbatch;
   const int ea = task % ne_all;  // (branch, element): elements of one q point are adjacent tasks
@@ -732,13 +782,13 @@ k_pcube(const Geom g, const Tabs tb, const PCube pc, const T *__restrict__ X, TO
     }
   }
   compact_inplace<T, NB1, CLOS>(g1, N1, T(g.dp_ca[0]), T(g.dp_cb[0]),
-                                CLOS ? tb.clos + 3 * 2 * kClosRows * kTab : nullptr);
+                                CLOS ? tb.clos + g.M * 2 * kClosRows * kTab : nullptr);
 #pragma unroll
   for (int i = 0; i < NB1; ++i) acc[i] += g1[i];
 
   // ---- phase B: the p_2 and p_3 terms in rounds of PL planes
-  const double *ct2 = CLOS ? tb.clos + (3 + 1) * 2 * kClosRows * kTab : nullptr;
-  const double *ct3 = CLOS ? tb.clos + (3 + 2) * 2 * kClosRows * kTab : nullptr;
+  const double *ct2 = CLOS ? tb.clos + (g.M + 1) * 2 * kClosRows * kTab : nullptr;
+  const double *ct3 = CLOS ? tb.clos + (g.M + 2) * 2 * kClosRows * kTab : nullptr;
   // round loads: the p_2 and p_3 neighbours of PL planes (planes past the
   // block re-read its last plane: in bounds, unused)
   auto load_round = [&](const int r, T (&u2)[PL], T (&d2)[PL], T (&u3)[PL], T (&d3)[PL]) {
@@ -779,10 +829,10 @@ k_pcube(const Geom g, const Tabs tb, const PCube pc, const T *__restrict__ X, TO
         const int l = hl >> 1;
         if (l < nl2) {
           const int k = l / N3, c = l - k * N3;
-          compact_split<T, NB1, CLOS>(G2, k * N2 * rs + c, rs, hl & 1, T(g.dp_ca[1]), T(g.dp_cb[1]), ct2);
+          compact_split_regs<T, NB1, CLOS>(G2, k * N2 * rs + c, rs, hl & 1, T(g.dp_ca[1]), T(g.dp_cb[1]), ct2);
         } else {
           const int l3 = l - nl2;
-          compact_split<T, NB1, CLOS>(G3, l3 * rs, 1, hl & 1, T(g.dp_ca[2]), T(g.dp_cb[2]), ct3);
+          compact_split_regs<T, NB1, CLOS>(G3, l3 * rs, 1, hl & 1, T(g.dp_ca[2]), T(g.dp_cb[2]), ct3);
         }
       }
     } else {

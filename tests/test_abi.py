@@ -104,13 +104,15 @@ def test_null_context_calls_are_rejected(binding):
 
 
 def test_p_block_tiling_limit_is_enforced(binding):
-    # the last two p axes are one LDS tile: N_{M-1} needs a divisor d with
-    # d * N_M <= 256 and N_{M-1} <= 4 d, otherwise rows would go uncovered
+    # the last two p axes are one LDS tile of k_pblock: N_{M-1} needs a
+    # divisor d with d * N_M <= 256 and N_{M-1} <= 4 d; shapes it cannot
+    # cover go to k_pcube when its workgroup holds the block (two modes: p_1
+    # lines of up to 48 points over a row of p_2 threads), else are refused
     w = wl.workload("two_mode_32")
-    for n, ok in ((16, True), (17, False), (24, True), (25, False), (32, True), (33, False), (48, False)):
+    for n in (16, 17, 24, 25, 31, 32, 33, 40, 47, 48):
         p = binding.params_from_workload(w)
         p.Np[0], p.Np[1] = n, n
-        assert (binding.workspace_bytes(p) > 0) == ok, n
+        assert binding.workspace_bytes(p) > 0, n
     p = binding.params_from_workload(w)
     p.Np[0], p.Np[1] = 17, 8        # 17 rows: divisor 17 with 17 * 8 <= 256
     assert binding.workspace_bytes(p) > 0
@@ -118,6 +120,12 @@ def test_p_block_tiling_limit_is_enforced(binding):
     assert binding.workspace_bytes(p) > 0
     one = binding.params_from_workload(wl.workload("one_mode_48"))
     assert binding.workspace_bytes(one) > 0    # one mode: rows of one p axis only
+    w3 = wl.workload("three_mode_24", Nq=[5, 5, 5])
+    for np3, ok in (((24, 24, 24), True), ((24, 25, 25), True), ((16, 25, 25), False), ((20, 30, 30), False),
+                    ((33, 25, 25), False)):
+        p = binding.params_from_workload(w3)
+        p.Np[0], p.Np[1], p.Np[2] = np3
+        assert (binding.workspace_bytes(p) > 0) == ok, np3
 
 
 def test_batch_beyond_one_dispatch_is_rejected(binding):

@@ -59,6 +59,9 @@ SMALL = {
     "m1_n12_k3": wl.workload("one_mode_48", Nq=[12], Np=[13], K=3),
     "m2_n10_k2": wl.workload("two_mode_32", Nq=[10, 9], Np=[11, 10], K=2),
     "m2_n12_k3": wl.workload("two_mode_32", Nq=[12, 12], Np=[12, 12], K=3),
+    # p blocks beyond the two-axis LDS tile: k_pcube with a unit third axis
+    "m2_p40_k2": wl.workload("two_mode_32", Nq=[6, 7], Np=[40, 36], K=2),
+    "m2_p48_k2": wl.workload("two_mode_32", Nq=[5, 6], Np=[48, 48], K=2),
     "m3_n8_k2": wl.workload("three_mode_24", Nq=[8, 7, 8], Np=[8, 9, 7], K=2),
     "m3_n6_k3": wl.workload("three_mode_24", Nq=[6, 6, 6], Np=[6, 6, 6], K=3),
     # square 8 x 8 (p_2, p_3) blocks: lane-pair line solves, ragged q and p_1
@@ -74,6 +77,16 @@ SMALL = {
 }
 
 THREE = [n for n in SMALL if n.startswith("m3")]
+
+
+def test_the_planner_takes_k_pcube_where_it_should(pk):
+    """Three modes take k_pcube wherever its block fits; two modes only for
+    p blocks the two-axis tile cannot cover; one mode never."""
+    want = {"m1_n12_k3": 0, "m2_n10_k2": 0, "m2_n12_k3": 0, "m2_p40_k2": 1, "m2_p48_k2": 1,
+            "m3_n8_k2": 1, "m3_p24_k2": 0, "m3_c24_k2": 1}
+    for name, flag in want.items():
+        with solver(pk, SMALL[name]) as s:
+            assert s.tile_config()["pcube"] == flag, name
 
 
 @pytest.mark.parametrize("name", THREE)
