@@ -119,7 +119,7 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(w, solver, target_s: float):
+def cpu_baseline(w, solver, target_s: float, name: str):
     """Time the FP64 CPU oracle on this workload's full state and compare the
     GPU's result for the same work (relative L2).  States above 5e8 values:
     one right-hand side (an RK4 step is four), else RK4 steps for about
@@ -165,7 +165,39 @@ def cpu_baseline(w, solver, target_s: float):
         "sample": sample,
         "cpu_model": cpu_model(),
         "nproc": os.cpu_count(),
+        "one_thread": one_thread_rate(name),
     }, err, n_cmp
+
+
+def oracle_one_thread(name: str) -> dict:
+    """One oracle right-hand side, timed in this process (run it with
+    OMP_NUM_THREADS=1), on the workload with every axis halved: same modes
+    and depth, 1/2^(2M) of the points."""
+    import oracle as orc
+    import workloads as wl
+    w = wl.workload(name)
+    h = wl.workload(name, Nq=[max(4, n // 2) for n in w["Nq"]], Np=[max(4, n // 2) for n in w["Np"]])
+    W0 = orc.boltzmann(h)
+    W0[1] = 0.2 * W0[0]
+    t0 = time.perf_counter()
+    orc.rhs(h, W0)
+    t = time.perf_counter() - t0
+    return {"value": W0.size / (4.0 * t), "unit": "updates/s", "threads": orc.num_threads(),
+            "sample": f"one oracle right-hand side ({t:.1f} s) of the {name} workload with every "
+                      f"axis halved (Nq {h['Nq']}, Np {h['Np']}, {W0.size} values); updates/s = values / (4 x time)"}
+
+
+def one_thread_rate(name: str):
+    """oracle_one_thread in a child process limited to one OpenMP thread
+    (None if that run fails)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--mode", "oracle1", "--workload", name],
+                           env=env, capture_output=True, text=True, timeout=300)
+        return json.loads(r.stdout.strip().splitlines()[-1]) if r.returncode == 0 else None
+    except (subprocess.SubprocessError, ValueError, IndexError):
+        return None
 
 
 
@@ -189,8 +221,8 @@ def _kind_of(short: str, grid: int, min_grid: dict):
     targs = [a.strip() for a in short[short.find("<") + 1:short.rfind(">")].split(",")] if "<" in short else []
     if fam == "k_pblock":
         kind = "perturb" if targs[5] == "true" else "pblock_rhs"  # <T, TO, NMAX, RPT, MM, PERTURB, CLOS>
-    elif fam == "k_pcube":
-        kind = "perturb" if targs[4] == "true" else "pcube_rhs"  # <T, TO, NB1, SPLIT, PERTURB, CLOS>
+    elif fam in ("k_pcube", "k_pcube_s"):
+        kind = "perturb" if targs[4] == "true" else "pcube_rhs"  # <T, TO, NB1, SPLIT, PERTURB[, CLOS]>
     elif fam == "k_qpass":
         if int(targs[5]) == 2:        # dX/dq field: second launch of a perturbation
             kind = "perturb_q"
@@ -472,7 +504,7 @@ def main(argv=None):
                     help="NB,SPLIT,PC[,RUN]: fixed tile shapes (k_pblock blocks per task, lane-pair "
                          "line solves 0/1, q-pass run positions per tile, k_pblock block groups "
                          "per state in task order) instead of autotuning")
-    ap.add_argument("--mode", choices=["bench", "kernels", "rk4", "summarise", "precision", "closure"],
+    ap.add_argument("--mode", choices=["bench", "kernels", "rk4", "summarise", "precision", "closure", "oracle1"],
                     default="bench",
                     help="kernels: a few RK4 steps of the workload (single state, then one "
                          "batched wave) plus a plain copy of known size, for hardware-counter "
@@ -516,6 +548,10 @@ def main(argv=None):
     args = ap.parse_args(argv)
     if args.mode == "summarise":
         return summarise(args)
+    if args.mode == "oracle1":  # the CPU oracle alone (cpu_baseline's one-thread figure); no GPU
+        import workloads as wl
+        print(json.dumps(oracle_one_thread(args.workload)), flush=True)
+        return 0
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the build targets a "
@@ -881,7 +917,7 @@ def main(argv=None):
     parity = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
-        cpu, parity, parity_of = cpu_baseline(w, solver, args.cpu_seconds)
+        cpu, parity, parity_of = cpu_baseline(w, solver, args.cpu_seconds, args.workload)
         cpu["sample"] += f"; the GPU result of the same work: relative L2 {parity:.1e} ({parity_of})"
     solver.close()
 

@@ -298,8 +298,10 @@ int chfpe_autotune(chfpe_ctx *ctx, int32_t n_steps);
  * variables reproduce; out[9] the k_pblock task order (consecutive block
  * groups of one state before the next element) and out[10] its request
  * (0 = 1; CHFPE_TUNE_PB_RUN); out[11] 1 when one workgroup per q point takes
- * the whole p block (k_pcube; out[0], out[9] then describe no launch).
- * Writes min(n, 12) values and returns that count. */
+ * the whole p block (k_pcube; out[0], out[9] then describe no launch), out[12]
+ * 1 when that kernel is the streamed form k_pcube_s (the default for p_1
+ * axes up to 16 points; CHFPE_TUNE_PC_STREAM=0/1 forces either form).
+ * Writes min(n, 13) values and returns that count. */
 int chfpe_tile_config(const chfpe_ctx *ctx, int32_t *out, int32_t n);
 
 /* ---- Learned per-axis closure (coarse grids) -------------------------------

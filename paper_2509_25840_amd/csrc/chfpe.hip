@@ -306,7 +306,7 @@ struct Launch {
   bool has_qa = false, qf_two = false, has_qx = false;
   // three modes: all p axes of a q point in one k_pcube task (then the q
   // passes are (q_2, q_3) and q_1 alone, and excitations need no qx)
-  bool pcube = false, pcube_split = false;
+  bool pcube = false, pcube_split = false, pcube_stream = false;
   PCube pcb{};
   int pcube_threads = 0, pcube_nb1 = 0;
   size_t pcube_lds = 0;
@@ -367,6 +367,7 @@ struct chfpe_ctx {
   int tune_pb_split = -1;  // k_pblock lines solved by lane pairs (-1: automatic)
   int tune_pb_run = 0;     // k_pblock consecutive block groups per state in task order (0: 1)
   int tune_pc_pad = 0;     // k_pcube LDS plane row pad (0: 1)
+  int tune_pc_stream = -1;  // k_pcube_s (1) or k_pcube (0); -1: by the p_1 length
   bool capturing = false;  // a HIP graph is being captured: no event timing
   bool closure_on = false; // right-hand sides use the closure stencil weights (tb.clos)
   bool use_graphs = true;
@@ -609,10 +610,16 @@ void plan_one(chfpe_ctx *c, int a, int run, std::vector<int> rest, QPass &out, i
 }
 
 // LDS of a k_pcube workgroup: a copy of the task's p block, and two fields
-// of one round's (p_2, p_3) planes with rows of N_3 + pad values.
-size_t pcube_lds_bytes(const Derived &d, size_t tsize, int pad) {
-  const int pl = pcube_planes(nmax_bucket(d.Np[0]));
-  return ((size_t)d.P + 2 * (size_t)pl * d.Np[1] * (size_t)(pcube_n3(d) + pad)) * tsize;
+// of one round's (p_2, p_3) planes with rows of N_3 + pad values.  The
+// streamed form (k_pcube_s) keeps no copy: its planes, and the first
+// forward results of every p_1 line.
+size_t pcube_lds_bytes(const Derived &d, size_t tsize, int pad, bool stream) {
+  const int nb1 = nmax_bucket(d.Np[0]);
+  const size_t rows = (size_t)d.Np[1] * (size_t)(pcube_n3(d) + pad);
+  if (stream)
+    return (kPCubeCF + 2 * (size_t)pcube_s_planes(nb1) * rows +
+            (size_t)pcube_s_dlds((int)tsize, nb1) * d.Np[1] * pcube_n3(d)) * tsize;
+  return ((size_t)d.P + 2 * (size_t)pcube_planes(nb1) * rows) * tsize;
 }
 
 // Three modes take k_pcube wherever its block fits (CHFPE_PCUBE=0 keeps the
@@ -690,10 +697,14 @@ bool plan(chfpe_ctx *c) {
     ln.pcube_nb1 = nmax_bucket(pq.N1);
     ln.pcube_threads = (pq.plane + 63) / 64 * 64;
     // row pad of the LDS planes (CHFPE_TUNE_PC_PAD, 1..8), kept only while the LDS fits
+    // the streamed form where its workgroups gain occupancy (p_1 up to 16
+    // points: four-wave workgroups); CHFPE_TUNE_PC_STREAM=0/1 forces either
+    ln.pcube_stream = c->tune_pc_stream >= 0 ? (c->tune_pc_stream > 0 && nmax_bucket(d.Np[0]) <= 32)
+                                             : nmax_bucket(d.Np[0]) <= 16;
     pq.rs = pq.N3 + 1;
-    if (c->tune_pc_pad > 1 && pcube_lds_bytes(d, sizeof(double), c->tune_pc_pad) <= 160 * 1024)
+    if (!ln.pcube_stream && c->tune_pc_pad > 1 && pcube_lds_bytes(d, sizeof(double), c->tune_pc_pad, false) <= 160 * 1024)
       pq.rs = pq.N3 + c->tune_pc_pad;
-    ln.pcube_lds = pcube_lds_bytes(d, sizeof(double), pq.rs - pq.N3);
+    ln.pcube_lds = pcube_lds_bytes(d, sizeof(double), pq.rs - pq.N3, ln.pcube_stream);
     ln.pcube_split = pq.N1 == ln.pcube_nb1 && pq.N2 == pq.N1 && pq.N3 == pq.N1 && c->tune_pb_split != 0;
     pb.nb = 1;  // k_pblock is not launched: one shape for the autotuner
     pb.split = ln.pcube_split ? 1 : 0;
@@ -882,23 +893,34 @@ void launch_pblock_t(chfpe_ctx *c, const Batch &b, const T *X, TO *out, const do
   }
 }
 
+template <typename K, typename T, typename TO>
+void launch_pcube_k(chfpe_ctx *c, K kern, size_t lds, const Batch &b, const T *X, TO *out, const double *grad) {
+  allow_lds(kern, lds);
+  hipLaunchKernelGGL(kern, dim3(b.pcb.nblk), dim3(c->ln.pcube_threads), lds, c->stream, b.g, c->tb, b.pcb,
+                     X, out, grad);
+}
+
+// k_pcube, or its streamed form k_pcube_s where the plan chose it (p_1 axes
+// up to 32 points, plain stencils; closure tables take k_pcube)
 template <typename T, typename TO, int NB1, bool SPLIT, bool PERTURB>
 void launch_pcube_s(chfpe_ctx *c, const Batch &b, const T *X, TO *out, const double *grad) {
-  const Launch &ln = c->ln;
-  const size_t lds = pcube_lds_bytes(c->d, sizeof(T), b.pcb.rs - b.pcb.N3);
+  const int pad = b.pcb.rs - b.pcb.N3;
   if constexpr (kClosureBuilt<T, TO, NB1>) {
     if (c->closure_on) {
-      auto kern = k_pcube<T, TO, NB1, SPLIT, PERTURB, true>;
-      allow_lds(kern, lds);
-      hipLaunchKernelGGL(kern, dim3(b.pcb.nblk), dim3(ln.pcube_threads), lds, c->stream, b.g, c->tb, b.pcb, X,
-                         out, grad);
+      launch_pcube_k(c, k_pcube<T, TO, NB1, SPLIT, PERTURB, true>, pcube_lds_bytes(c->d, sizeof(T), pad, false),
+                     b, X, out, grad);
       return;
     }
   }
-  auto kern = k_pcube<T, TO, NB1, SPLIT, PERTURB>;
-  allow_lds(kern, lds);
-  hipLaunchKernelGGL(kern, dim3(b.pcb.nblk), dim3(ln.pcube_threads), lds, c->stream, b.g, c->tb, b.pcb, X, out,
-                     grad);
+  if constexpr (NB1 <= 32) {
+    if (c->ln.pcube_stream) {
+      launch_pcube_k(c, k_pcube_s<T, TO, NB1, SPLIT, PERTURB>, pcube_lds_bytes(c->d, sizeof(T), pad, true), b, X,
+                     out, grad);
+      return;
+    }
+  }
+  launch_pcube_k(c, k_pcube<T, TO, NB1, SPLIT, PERTURB>, pcube_lds_bytes(c->d, sizeof(T), pad, false), b, X, out,
+                 grad);
 }
 
 template <typename T, typename TO, int NB1, bool PERTURB>
@@ -1476,6 +1498,7 @@ int chfpe_setup(const chfpe_params *p, void *dev_workspace, size_t ws_bytes, voi
   if (const char *v = std::getenv("CHFPE_TUNE_PB_SPLIT")) c->tune_pb_split = std::atoi(v);
   if (const char *v = std::getenv("CHFPE_TUNE_PB_RUN")) c->tune_pb_run = std::atoi(v);
   if (const char *v = std::getenv("CHFPE_TUNE_PC_PAD")) c->tune_pc_pad = std::max(0, std::min(8, std::atoi(v)));
+  if (const char *v = std::getenv("CHFPE_TUNE_PC_STREAM")) c->tune_pc_stream = std::atoi(v);
   if (const char *v = std::getenv("CHFPE_NO_GRAPH")) c->use_graphs = std::atoi(v) == 0;
   if (const char *v = std::getenv("CHFPE_PCUBE")) c->allow_pcube = std::atoi(v) != 0;
   std::vector<double> F, Vp, pm, pg, sq, sp, wp, cc, tc, damp;
@@ -1989,11 +2012,11 @@ int chfpe_autotune(chfpe_ctx *c, int32_t n_steps) {
 
 int chfpe_tile_config(const chfpe_ctx *c, int32_t *out, int32_t n) {
   if (!c || !out || n < 0) return CHFPE_EINVAL;
-  const int32_t v[12] = {c->ln.pb.nb,  c->ln.pb.split,    c->ln.pb_threads,
+  const int32_t v[13] = {c->ln.pb.nb,  c->ln.pb.split,    c->ln.pb_threads,
                          c->ln.qf.pc,  c->ln.has_qa ? c->ln.qa.pc : 0, c->ln.qf_threads,
                          c->tune_pb_nb, c->tune_pb_split, c->tune_q_pc, c->ln.pb.run, c->tune_pb_run,
-                         c->ln.pcube ? 1 : 0};
-  const int k = n < 12 ? n : 12;
+                         c->ln.pcube ? 1 : 0, c->ln.pcube && c->ln.pcube_stream ? 1 : 0};
+  const int k = n < 13 ? n : 13;
   for (int i = 0; i < k; ++i) out[i] = v[i];
   return k;
 }

@@ -66,6 +66,16 @@ constexpr ThomasTable make_thomas() {
 
 constexpr ThomasTable kThomas = make_thomas();
 
+// Fused multiply-add in the arithmetic type (the double builtin would
+// widen a float operation).
+template <typename T>
+__device__ __forceinline__ T fma_t(const T a, const T b, const T c) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_fmaf(a, b, c);
+  else
+    return __builtin_fma(a, b, c);
+}
+
 // Right-hand side of the compact scheme at position i of a line,
 //   (1/3) f'_{i-1} + f'_i + (1/3) f'_{i+1}
 //       = ca (f_{i+1} - f_{i-1}) + cb (f_{i+2} - f_{i-2}),  ca = 7/(9h), cb = 1/(36h),
@@ -264,7 +274,7 @@ __device__ __forceinline__ void compact_split(T *G, const int base, const int st
     const T fp3 = CLOS ? f[i + 3 < NL ? i + 3 : NL - 1] : T(0);
     const T r = stencil_rhs<T, CLOS>(i, fm3, fm2, fm1, f[i + 1], f[i + 2], fp3, ca, cb, cto);
     // d_i = (r_i - d_{i-1}/3) / pivot_i, one dependent FMA
-    const T d = i == 0 ? r : __builtin_fma(T(-kThomas.inv[i] / 3.0), dprev, r * T(kThomas.inv[i]));
+    const T d = i == 0 ? r : fma_t(T(-kThomas.inv[i] / 3.0), dprev, r * T(kThomas.inv[i]));
     G[start + i * step] = d;
     dprev = d;
   }
@@ -316,7 +326,7 @@ __device__ __forceinline__ void compact_split_regs(T *G, const int base, const i
     const T fm3 = (CLOS && i >= 3) ? f[i >= 3 ? i - 3 : 0] : T(0);
     const T fp3 = CLOS ? f[i + 3 < NL ? i + 3 : NL - 1] : T(0);
     const T r = stencil_rhs<T, CLOS>(i, fm3, fm2, fm1, f[i + 1], f[i + 2], fp3, ca, cb, cto);
-    d[i] = i == 0 ? r : __builtin_fma(T(-kThomas.inv[i] / 3.0), d[i >= 1 ? i - 1 : 0], r * T(kThomas.inv[i]));
+    d[i] = i == 0 ? r : fma_t(T(-kThomas.inv[i] / 3.0), d[i >= 1 ? i - 1 : 0], r * T(kThomas.inv[i]));
   }
   const T other = __shfl_xor(d[H - 1], 1);
   T x = (d[H - 1] - T(cm) * other) * T(inv1mc2);
@@ -869,6 +879,253 @@ k_pcube(const Geom g, const Tabs tb, const PCube pc, const T *__restrict__ X, TO
 #pragma unroll
   for (int i = 0; i < NB1; ++i)
     if (i < N1) at_u32(Oe, (uint32_t)(i * plane + tid)) = TO(acc[i]);
+}
+
+// ---------------------------------------------------------------------------
+// k_pcube_s: k_pcube in one streamed sweep over the planes
+// ---------------------------------------------------------------------------
+// Same task, thread map and result as k_pcube.  Along a p_1 line, with s_i
+// the pointwise, p_2 and p_3 terms of plane i and G_1 the p_1 field, the
+// right-hand side is
+//   t = s + A^{-1} B G_1 = A^{-1} (A s + B G_1),
+// A = tridiag(1/3, 1, 1/3), B the explicit stencil.  Plane i, once its p_2
+// and p_3 lines are solved, adds s_i and G_{1,i} to the rows r_{i-R}..r_{i+R}
+// of A t = r that they touch (R = stencil reach), and row i - R, now
+// complete, takes its forward Thomas step.  Every value is read once (no copy
+// of the block), so the LDS holds only a round's two planes and the first ND
+// forward results d_j of every line (the rest stay in registers); the back
+// substitution then writes t.  At 24^3 in FP64 that is 78 KB of LDS and
+// 96 VGPRs: two workgroups per CU, where k_pcube's block copy allows one.
+// Plain stencils only (a closure keeps k_pcube).
+
+// Task constants of k_pcube_s in LDS: slots of the groups below (three
+// modes each) and the damping, then the p_2 and p_3 grids.
+constexpr int kCfF = 0, kCfVu = 3, kCfVd = 6, kCfPu = 9, kCfPd = 12, kCfBm = 15, kCfDamp = 18;
+constexpr int kCfP2 = 20, kCfP3 = kCfP2 + kTab;
+constexpr int kPCubeCF = kCfP3 + kTab;
+constexpr int pcube_s_planes(const int nb1) { return nb1 >= 24 ? 2 : nb1 / 4; }
+constexpr int pcube_s_dlds(const int tsize, const int nb1) { return tsize == 8 && nb1 >= 24 ? nb1 / 2 + 1 : 0; }
+// Waves per SIMD the register budget aims at: five for the cubic FP64 24^3
+// block (two workgroups of nine waves per CU).
+template <typename T, int NB1, bool SPLIT>
+constexpr int pcube_s_waves() {
+  return sizeof(T) == 8 && NB1 == 24 && SPLIT ? 5 : 4;
+}
+
+template <typename T, typename TO, int NB1, bool SPLIT, bool PERTURB>
+__global__ void __launch_bounds__((pcube_max_threads<T, NB1>()), (pcube_s_waves<T, NB1, SPLIT>()))
+k_pcube_s(const Geom g, const Tabs tb, const PCube pc, const T *__restrict__ X, TO *__restrict__ out,
+          const double *__restrict__ grad) {
+  constexpr int PL = pcube_s_planes(NB1);          // planes per round
+  constexpr int NR = (NB1 + PL - 1) / PL;          // rounds
+  constexpr int ND = pcube_s_dlds(sizeof(T), NB1);  // forward results kept in LDS
+  constexpr int RC = 2;                            // stencil reach along p_1
+  constexpr T third = T(1.0 / 3.0);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int task = xcd_task(blockIdx.x, pc.nblk);
+  if (task >= pc.ntasks) return;
+  // SPLIT blocks are cubes of NB1 points: their loops have fixed trip counts
+  const int N1 = SPLIT ? NB1 : pc.N1, N2 = SPLIT ? NB1 : pc.N2, N3 = SPLIT ? NB1 : pc.N3;
+  const int plane = SPLIT ? NB1 * NB1 : pc.plane;
+  const int rs = SPLIT ? NB1 + 1 : pc.rs;  // LDS row stride (p_3 row plus a pad)
+  T *CF = reinterpret_cast<T *>(smem_raw);  // task constants, kPCubeCF values
+  T *G2 = CF + kPCubeCF;                    // [PL][N2][rs]
+  T *G3 = G2 + PL * N2 * rs;
+  T *Dl = G3 + PL * N2 * rs;                // [ND][plane]
+  const int ne_all = g.ne * g.nbatch;
+  const int ea = task % ne_all;  // (branch, element): elements of one q point are adjacent tasks
+  const int ql = task / ne_all;
+  const int br = ea / g.ne;
+  const int e = ea - br * g.ne;
+  const int tid = threadIdx.x;
+  const bool own = tid < plane;
+  const int j2 = own ? tid / N3 : 0;
+  const int j3 = own ? tid - j2 * N3 : 0;
+  const int Q = g.Q;
+
+  const long long blk = (long long)ql * g.P;
+  const T *Xe = X + (long long)ea * g.E + blk;
+  TO *Oe = out + (long long)ea * g.E + blk;
+  const T *Xb = X + (long long)br * g.ne * g.E;
+  // A missing neighbour points at the element itself and has zero factors,
+  // so the neighbour loads are unconditional (no per-neighbour branch or
+  // mask; the repeated address is served by the cache).
+  const T *Xu[3];
+  const T *Xd[3];
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const int up = PERTURB ? -1 : tb.up[e * 3 + s];
+    const int dn = PERTURB ? -1 : tb.dn[e * 3 + s];
+    Xu[s] = up >= 0 ? Xb + (long long)up * g.E + blk : Xe;
+    Xd[s] = dn >= 0 ? Xb + (long long)dn * g.E + blk : Xe;
+  }
+  // The task's constants go to LDS once and are read where they are used
+  // in every round, so that neither scalar nor vector registers hold them
+  // through the line solves: per mode s (slot s of each group of three)
+  // F_s (or dX/dq_s), V_s' for n + e_s and n - e_s, and the p_s-weighted
+  // pointwise factors; then the damping and, for PERTURB, beta/2m_s dX/dq_s.
+  if (tid < 3) {
+    const int s = tid;
+    const int up = PERTURB ? -1 : tb.up[e * 3 + s];
+    if (PERTURB) {
+      const double gr = grad[s * Q + ql];
+      CF[kCfF + s] = T(gr);
+      CF[kCfVu + s] = CF[kCfVd + s] = CF[kCfPu + s] = CF[kCfPd + s] = T(0);
+      CF[kCfBm + s] = T(gr * g.bm[s]);
+    } else {
+      const double vp = tb.VpQ[s * Q + ql];
+      CF[kCfF + s] = T(tb.F[s * Q + ql]);
+      CF[kCfVu + s] = up >= 0 ? T(vp) : T(0);
+      CF[kCfVd + s] = T(vp * tb.cc[e * 3 + s]);         // zero when n_s = 0
+      CF[kCfPd + s] = T(vp * 0.5 * tb.tc[e * 3 + s]);  // times p_s
+      CF[kCfPu + s] = up >= 0 ? T(vp * g.bm[s]) : T(0);
+      CF[kCfBm + s] = T(0);
+    }
+    if (s == 0) CF[kCfDamp] = PERTURB ? T(0) : T(tb.damp[e]);
+  }
+  if (tid < N2) CF[kCfP2 + tid] = T(tb.pg[1 * kTab + tid]);
+  if (tid < N3) CF[kCfP3 + tid] = T(tb.pg[2 * kTab + tid]);
+  __syncthreads();
+  const T ca1 = T(g.dp_ca[0]), cb1 = T(g.dp_cb[0]);
+  const uint32_t own_off = (uint32_t)(own ? tid : 0);
+
+  // ln[j]: row j of A t = r while it collects its terms, then its forward
+  // result d_j (rows j < ND move to Dl once eliminated)
+  T ln[NB1];
+#pragma unroll
+  for (int j = 0; j < NB1; ++j) ln[j] = T(0);
+  T dprev = T(0);
+  auto elim = [&](const int j) {
+    const T d = j == 0 ? ln[j] : fma_t(T(-kThomas.inv[j] / 3.0), dprev, ln[j] * T(kThomas.inv[j]));
+    dprev = d;
+    if (j < ND) {
+      if (own) Dl[j * plane + tid] = d;
+    } else {
+      ln[j] = d;
+    }
+  };
+
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int i0 = r * PL;
+    if (i0 >= N1) break;  // uniform
+    // h_n and its six neighbours on PL planes: pointwise terms and G_1 stay
+    // in registers, G_2 and G_3 go to the LDS planes.  The thread's p_2, p_3
+    // factors are formed again in every round from the LDS copies.
+    const T p2 = CF[kCfP2 + j2], p3 = CF[kCfP3 + j3];
+    T Fv[3], vu[3], vd[3];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      Fv[s] = CF[kCfF + s];
+      vu[s] = CF[kCfVu + s];
+      vd[s] = CF[kCfVd + s];
+    }
+    const T dmp = CF[kCfDamp], pwu1 = CF[kCfPu], pwd1 = CF[kCfPd];
+    const T c1 = CF[kCfBm], c23 = CF[kCfBm + 1] * T(p2) + CF[kCfBm + 2] * T(p3);
+    const T q2u = T(p2) * CF[kCfPu + 1], q2d = T(p2) * CF[kCfPd + 1];
+    const T q3u = T(p3) * CF[kCfPu + 2], q3d = T(p3) * CF[kCfPd + 2];
+    T sv[PL], gv[PL];
+#pragma unroll
+    for (int k = 0; k < PL; ++k) {
+      const int i = i0 + k;
+      sv[k] = gv[k] = T(0);
+      if (i < N1) {
+        // the offset is hidden from the optimiser so that every load takes
+        // the scalar-base form (one 32-bit offset register) rather than a
+        // 64-bit address per neighbour held through the kernel
+        uint32_t o = (uint32_t)(i * plane) + own_off;
+        asm volatile("" : "+v"(o));
+        const T h = at_u32(Xe, o);
+        const T p1 = T(tb.pg[0 * kTab + i]);
+        T f2 = Fv[1] * h, f3 = Fv[2] * h;
+        if (PERTURB) {
+          sv[k] = -(c23 + c1 * p1) * h;
+          gv[k] = Fv[0] * h;
+        } else {
+          const T u1 = at_u32(Xu[0], o), d1 = at_u32(Xd[0], o);
+          const T u2 = at_u32(Xu[1], o), d2 = at_u32(Xd[1], o);
+          const T u3 = at_u32(Xu[2], o), d3 = at_u32(Xd[2], o);
+          sv[k] = -dmp * h + p1 * (pwd1 * d1 - pwu1 * u1) + q2d * d2 - q2u * u2 + q3d * d3 - q3u * u3;
+          gv[k] = Fv[0] * h + vu[0] * u1 + vd[0] * d1;
+          f2 += vu[1] * u2 + vd[1] * d2;
+          f3 += vu[2] * u3 + vd[2] * d3;
+        }
+        if (own) {
+          const int li = (k * N2 + j2) * rs + j3;
+          G2[li] = f2;
+          G3[li] = f3;
+        }
+      }
+      // keep sv, gv computed here: sunk past the barrier, their seven
+      // inputs per plane would stay live (in registers) through the solves
+      asm volatile("" : "+v"(sv[k]), "+v"(gv[k]));
+    }
+    __syncthreads();
+    // p_2 lines of G2 (fixed k, j3) and p_3 lines of G3 (fixed k, j2)
+    const int npl = min(PL, N1 - i0);
+    const int nl2 = npl * N3, nl = nl2 + npl * N2;
+    if (SPLIT) {
+#pragma unroll 1
+      for (int hl = tid; hl < 2 * nl; hl += blockDim.x) {
+        const int l = hl >> 1;
+        if (l < nl2) {
+          const int k = l / N3, c = l - k * N3;
+          compact_split<T, NB1>(G2, k * N2 * rs + c, rs, hl & 1, T(g.dp_ca[1]), T(g.dp_cb[1]));
+        } else {
+          compact_split<T, NB1>(G3, (l - nl2) * rs, 1, hl & 1, T(g.dp_ca[2]), T(g.dp_cb[2]));
+        }
+      }
+    } else {
+#pragma unroll 1
+      for (int l = tid; l < nl; l += blockDim.x) {
+        if (l < nl2) {
+          const int k = l / N3, c = l - k * N3;
+          compact_lds<T>(G2, k * N2 * rs + c, rs, N2, T(g.dp_ca[1]), T(g.dp_cb[1]));
+        } else {
+          compact_lds<T>(G3, (l - nl2) * rs, 1, N3, T(g.dp_ca[2]), T(g.dp_cb[2]));
+        }
+      }
+    }
+    __syncthreads();
+    // fold each plane into the p_1 rows it touches, oldest plane first
+#pragma unroll
+    for (int k = 0; k < PL; ++k) {
+      const int i = i0 + k;
+      if (i < N1) {
+        const int li = (k * N2 + j2) * rs + j3;
+        const T s = sv[k] + G2[li] + G3[li];
+        const T gg = gv[k];
+        ln[i] += s;  // A s
+        if (i >= 1) ln[i >= 1 ? i - 1 : 0] += third * s;
+        if (i + 1 < NB1) ln[i + 1 < NB1 ? i + 1 : 0] += third * s;
+        // B G_1: row j takes ca (G_{j+1} - G_{j-1}) + cb (G_{j+2} - G_{j-2})
+        if (i >= 1) ln[i >= 1 ? i - 1 : 0] += ca1 * gg;
+        if (i >= 2) ln[i >= 2 ? i - 2 : 0] += cb1 * gg;
+        if (i + 1 < NB1) ln[i + 1 < NB1 ? i + 1 : 0] -= ca1 * gg;
+        if (i + 2 < NB1) ln[i + 2 < NB1 ? i + 2 : 0] -= cb1 * gg;
+        if (i >= RC) elim(i >= RC ? i - RC : 0);  // row i - R has all its terms
+        if (i == N1 - 1) {                        // last plane: the remaining rows
+#pragma unroll
+          for (int kk = RC - 1; kk >= 0; --kk)
+            if (i - kk >= 0) elim(i - kk >= 0 ? i - kk : 0);
+        }
+      }
+    }
+    __syncthreads();  // the next round overwrites the planes
+  }
+  if (!own) return;
+  // back substitution from the far end of the line, writing t
+  T x = T(0);
+#pragma unroll
+  for (int j = NB1 - 1; j >= 0; --j) {
+    if (j < N1) {
+      const T d = j < ND ? Dl[j * plane + tid] : ln[j];
+      x = d - T(kThomas.cp[j]) * x;
+      uint32_t o = (uint32_t)(j * plane + tid);
+      asm volatile("" : "+v"(o));
+      at_u32(Oe, o) = TO(x);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------

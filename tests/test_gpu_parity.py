@@ -62,6 +62,7 @@ SMALL = {
     # p blocks beyond the two-axis LDS tile: k_pcube with a unit third axis
     "m2_p40_k2": wl.workload("two_mode_32", Nq=[6, 7], Np=[40, 36], K=2),
     "m2_p48_k2": wl.workload("two_mode_32", Nq=[5, 6], Np=[48, 48], K=2),
+    "m2_p25_k2": wl.workload("two_mode_32", Nq=[6, 5], Np=[25, 25], K=2),
     "m3_n8_k2": wl.workload("three_mode_24", Nq=[8, 7, 8], Np=[8, 9, 7], K=2),
     "m3_n6_k3": wl.workload("three_mode_24", Nq=[6, 6, 6], Np=[6, 6, 6], K=3),
     # square 8 x 8 (p_2, p_3) blocks: lane-pair line solves, ragged q and p_1
@@ -83,7 +84,7 @@ def test_the_planner_takes_k_pcube_where_it_should(pk):
     """Three modes take k_pcube wherever its block fits; two modes only for
     p blocks the two-axis tile cannot cover; one mode never."""
     want = {"m1_n12_k3": 0, "m2_n10_k2": 0, "m2_n12_k3": 0, "m2_p40_k2": 1, "m2_p48_k2": 1,
-            "m3_n8_k2": 1, "m3_p24_k2": 0, "m3_c24_k2": 1}
+            "m2_p25_k2": 1, "m3_n8_k2": 1, "m3_p24_k2": 0, "m3_c24_k2": 1}
     for name, flag in want.items():
         with solver(pk, SMALL[name]) as s:
             assert s.tile_config()["pcube"] == flag, name
@@ -100,6 +101,39 @@ def test_three_mode_p_block_path_matches_the_oracle(pk, monkeypatch, name):
     W = phys_state(w, seed=11)
     X = wl.optical(3, lin=[1.0, -0.7, 0.4], quad=[[0.2, 0.05, -0.03], [0.05, -0.1, 0.02], [-0.03, 0.02, 0.3]])
     with solver(pk, w) as s:
+        s.set_state(W)
+        s.rhs()
+        e_rhs = rel_l2(s.get_state(), orc.rhs(w, W))
+        s.set_state(W)
+        s.propagate(2, 0.002)
+        e_rk4 = rel_l2(s.get_state(), orc.rk4(w, W, 2, 0.002))
+        s.set_state(W)
+        s.perturb(X)
+        e_x = rel_l2(s.get_state(), orc.perturb(w, X, W))
+    say(f"    rhs {e_rhs:.2e} rk4 {e_rk4:.2e} perturb {e_x:.2e}")
+    assert e_rhs < 1e-13 and e_rk4 < 1e-13 and e_x < 1e-13
+
+
+PCUBE = ["m3_n8_k2", "m3_p8_k2", "m3_n6_k3", "m3_c8_k2", "m3_c12_k2", "m3_c24_k2", "m2_p25_k2"]
+
+
+@pytest.mark.parametrize("stream", [0, 1])
+@pytest.mark.parametrize("name", PCUBE)
+def test_both_k_pcube_forms_match_the_oracle(pk, monkeypatch, name, stream):
+    """k_pcube (a copy of the p block in LDS) and k_pcube_s (one streamed
+    sweep over the planes), each forced with CHFPE_TUNE_PC_STREAM, give the
+    oracle's right-hand side, RK4 steps and X^x (cubic blocks with lane-pair
+    plane solves, ragged blocks, and a two-mode block with a unit third axis)."""
+    monkeypatch.setenv("CHFPE_TUNE_PC_STREAM", str(stream))
+    w = SMALL[name]
+    M = w["M"]
+    say(f"[k_pcube stream={stream}] {name}")
+    W = phys_state(w, seed=12)
+    X = wl.optical(M, lin=[1.0, -0.7, 0.4][:M],
+                   quad=[r[:M] for r in [[0.2, 0.05, -0.03], [0.05, -0.1, 0.02], [-0.03, 0.02, 0.3]][:M]])
+    with solver(pk, w) as s:
+        cfg = s.tile_config()
+        assert cfg["pcube"] == 1 and cfg["pcube_stream"] == stream, cfg
         s.set_state(W)
         s.rhs()
         e_rhs = rel_l2(s.get_state(), orc.rhs(w, W))
