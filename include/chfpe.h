@@ -50,6 +50,7 @@ enum {
 };
 
 enum { CHFPE_FP64 = 0, CHFPE_FP32 = 1 };
+enum { CHFPE_BASIS_GRID = 0, CHFPE_BASIS_HERMITE = 1 };
 
 /*
  * Model and discretisation.
@@ -70,10 +71,26 @@ enum { CHFPE_FP64 = 0, CHFPE_FP32 = 1 };
  *     with batch > 1 or CHFPE_FP32, branches run in waves of `batch` states
  *     (batch x 4 extra state buffers of the branch type in the workspace),
  *     each wave's t2 loop as one captured HIP graph.
+ *   basis: discretisation of the momenta.  CHFPE_BASIS_GRID: the compact
+ *     scheme on a p grid (Np points on [-Lp, Lp]).  CHFPE_BASIS_HERMITE: the
+ *     paper's own Hermite-function expansion (Sec. III A; Appendix A, Eq.
+ *     (HEOM2FP-H)): W_n = e^{-beta U/2} prod_s psi_0(p_s) sum_k c_{n,k}(q)
+ *     prod_s psi_{k_s}(p_s), psi_j the Hermite functions of width
+ *     a_s = sqrt(2 m_s / beta); Np[s] is then the number of Hermite
+ *     functions of mode s (k_s < Np[s]) and Lp is not read.  Every call
+ *     below works in either basis; with the Hermite basis a state is the
+ *     coefficient array c[n][k_1..k_M][q_1..q_M] (q_M fastest), which
+ *     chfpe_get_state / chfpe_set_state copy as they are, observables
+ *     integrate p exactly (only c_{0,0} contributes), and there are no tile
+ *     shapes to tune (chfpe_autotune returns at once) and no closure.
  * Limits: 1 <= M <= 3, 0 <= K <= 12, 5 <= N <= 48 on every axis (the p
  * axes also within the tiling limit under chfpe_setup), all
  * masses, beta, L > 0, one element below 2^29 points, and
  * exp(-beta H_sys/2) representable (> 1e-150) everywhere on the grid.
+ * With the Hermite basis: 2 <= Np[s] <= 48, and the q cube of one task
+ * must fit one workgroup: a thread per (q_2, q_3) point (two modes: per q_2
+ * point) holding a q_1 line, at most 1024 / 768 / 512 / 256 threads for q_1
+ * lines of up to 16 / 24 / 32 / 48 points.
  */
 typedef struct {
   int32_t M;
@@ -96,6 +113,7 @@ typedef struct {
   double beta;
   int32_t precision;
   int32_t batch;
+  int32_t basis; /* CHFPE_BASIS_GRID or CHFPE_BASIS_HERMITE */
 } chfpe_params;
 
 /* Optical operator X(q) = sum_s lin_s q_s + 1/2 sum_{s,s'} quad_ss' q_s q_s'

@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libchfpe.so")
 
 CHFPE_OK, CHFPE_EINVAL, CHFPE_ENOMEM, CHFPE_EDEVICE, CHFPE_ENONFINITE, CHFPE_ESTATE = 0, -1, -2, -3, -4, -5
 CHFPE_FP64, CHFPE_FP32 = 0, 1
+CHFPE_BASIS_GRID, CHFPE_BASIS_HERMITE = 0, 1
 _CODES = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONFINITE", -5: "ESTATE"}
 
 _d3 = ctypes.c_double * 3
@@ -40,6 +41,7 @@ class Params(ctypes.Structure):
         ("g2", _d33), ("g21", _d33), ("g12", _d33),
         ("V_LL", _d3), ("V_SL", _d3), ("zeta", _d3), ("gamma", _d3),
         ("beta", ctypes.c_double), ("precision", ctypes.c_int32), ("batch", ctypes.c_int32),
+        ("basis", ctypes.c_int32),
     ]
 
 
@@ -143,7 +145,9 @@ def lib():
 
 def params_from_workload(w: dict, precision=None, batch: int = 0) -> Params:
     """chfpe_params from a workload dict (see ``workloads``); precision
-    defaults to the workload's ("f32" -> CHFPE_FP32, else CHFPE_FP64)."""
+    defaults to the workload's ("f32" -> CHFPE_FP32, else CHFPE_FP64), and
+    the p basis to its "basis" entry ("hermite" -> CHFPE_BASIS_HERMITE, Np
+    then counting Hermite functions; else the p grid)."""
     if precision is None:
         precision = CHFPE_FP32 if w.get("precision") == "f32" else CHFPE_FP64
     p = Params()
@@ -163,6 +167,7 @@ def params_from_workload(w: dict, precision=None, batch: int = 0) -> Params:
     p.beta = float(w["beta"])
     p.precision = int(precision)
     p.batch = int(batch)
+    p.basis = CHFPE_BASIS_HERMITE if w.get("basis") == "hermite" else CHFPE_BASIS_GRID
     return p
 
 

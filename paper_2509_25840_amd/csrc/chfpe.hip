@@ -43,7 +43,7 @@ constexpr int kQThreadsMax = 512;    // largest k_qpass workgroup
 
 // Kernel kinds for event timing; batched launches (several branch states per
 // launch) are kept apart from single-state ones.
-constexpr int kNumBase = 10;
+constexpr int kNumBase = 15;
 constexpr int kNumKinds = 2 * kNumBase;
 enum Kind : int {
   K_PBLOCK = 0,
@@ -55,23 +55,32 @@ enum Kind : int {
   K_OBSERVE = 6,
   K_PERTURB = 7,
   K_QOUT = 8,
-  K_PCUBE = 9
+  K_PCUBE = 9,
+  K_HS1 = 10,  // Hermite basis: one k_hcube launch per RK4 stage
+  K_HS2 = 11,
+  K_HS3 = 12,
+  K_HS4 = 13,
+  K_HOUT = 14
 };
 const char *kKindNames[kNumKinds] = {
     "pblock_rhs", "qpass_acc", "qpass_rk4_s1", "qpass_rk4_s2", "qpass_rk4_s3", "qpass_rk4_s4", "observe",
-    "perturb", "qpass_out", "pcube_rhs", "batch_pblock_rhs", "batch_qpass_acc", "batch_qpass_rk4_s1",
+    "perturb", "qpass_out", "pcube_rhs", "hcube_rk4_s1", "hcube_rk4_s2", "hcube_rk4_s3", "hcube_rk4_s4",
+    "hcube_out", "batch_pblock_rhs", "batch_qpass_acc", "batch_qpass_rk4_s1",
     "batch_qpass_rk4_s2", "batch_qpass_rk4_s3", "batch_qpass_rk4_s4", "batch_observe", "batch_perturb",
-    "batch_qpass_out", "batch_pcube_rhs"};
+    "batch_qpass_out", "batch_pcube_rhs", "batch_hcube_rk4_s1", "batch_hcube_rk4_s2", "batch_hcube_rk4_s3",
+    "batch_hcube_rk4_s4", "batch_hcube_out"};
 // state passes each kind reads plus writes (each input once, each output
 // once): the first stage reads its input (y) and t and writes z1; later
-// stages also read y (the last one reads and writes it in place)
-const double kKindPasses[kNumBase] = {2, 3, 3, 4, 4, 4, 0.1, 2, 3, 2};
+// stages also read y (the last one reads and writes it in place); a
+// Hermite stage reads its input (and y) and writes its output
+const double kKindPasses[kNumBase] = {2, 3, 3, 4, 4, 4, 0.1, 2, 3, 2, 2, 3, 3, 3, 2};
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Derived {
   int prec = 0, B = 1;    // precision of branch states; branches per wave
   bool batched = false;   // 2D responses use the batched branch buffers
+  bool hermite = false;   // Hermite basis in p: P counts Hermite functions, layout [n][k][q]
   int M = 0, K = 0, ne = 0;
   int Nq[3] = {0, 0, 0}, Np[3] = {0, 0, 0};  // axes s >= M stay 0
   int Q = 0, P = 0;
@@ -141,6 +150,32 @@ bool pcube_shape_ok(const Derived &d) {
          items <= 0xFFFFFFFFLL;
 }
 
+// The q cube of a k_hcube task (Hermite basis): q_1 lines (registers) of at
+// most 48 points, a (q_2, q_3) plane (two modes: a q_2 row; one mode: one
+// point) of threads within the workgroup bound of the q_1 bucket.
+int hcube_n2(const Derived &d) { return d.M >= 2 ? d.Nq[1] : 1; }
+int hcube_n3(const Derived &d) { return d.M == 3 ? d.Nq[2] : 1; }
+int hcube_max_threads_for(int nb1) {
+  return nb1 >= 48 ? hcube_max_threads<double, 48>()
+         : nb1 >= 32 ? hcube_max_threads<double, 32>()
+         : nb1 >= 24 ? hcube_max_threads<double, 24>() : hcube_max_threads<double, 16>();
+}
+bool hcube_shape_ok(const Derived &d, std::string &err) {
+  const int nb1 = nmax_bucket(d.Nq[0]);
+  const int thr = (hcube_n2(d) * hcube_n3(d) + 63) / 64 * 64;
+  if (thr > hcube_max_threads_for(nb1)) {
+    err = "Hermite basis: the (q_2, q_3) plane has more points than one workgroup for q_1 lines of " +
+          std::to_string(d.Nq[0]) + " points allows";
+    return false;
+  }
+  const long long items = grid_items((long long)d.ne * d.P * (d.batched ? d.B : 1), thr);
+  if (items > kMaxGridItems) {
+    err = "batch too large: a k_hcube launch over every branch state exceeds one dispatch (2^32 work-items)";
+    return false;
+  }
+  return true;
+}
+
 bool derive(const chfpe_params *p, Derived &d, std::string &err) {
   if (!p) {
     err = "params is NULL";
@@ -162,6 +197,11 @@ bool derive(const chfpe_params *p, Derived &d, std::string &err) {
     err = "batch must be in [0, 1024]";
     return false;
   }
+  if (p->basis != CHFPE_BASIS_GRID && p->basis != CHFPE_BASIS_HERMITE) {
+    err = "basis must be CHFPE_BASIS_GRID or CHFPE_BASIS_HERMITE";
+    return false;
+  }
+  d.hermite = p->basis == CHFPE_BASIS_HERMITE;
   d.prec = p->precision;
   d.B = p->batch > 0 ? p->batch : 1;
   d.batched = d.B > 1 || d.prec == CHFPE_FP32;
@@ -170,11 +210,13 @@ bool derive(const chfpe_params *p, Derived &d, std::string &err) {
   d.Q = 1;
   d.P = 1;
   for (int s = 0; s < p->M; ++s) {
-    if (p->Nq[s] < 5 || p->Nq[s] > kMaxAxis || p->Np[s] < 5 || p->Np[s] > kMaxAxis) {
-      err = "every axis needs 5 <= N <= 48 points";
+    const int np_lo = d.hermite ? 2 : 5;  // Hermite functions per mode, or p points
+    if (p->Nq[s] < 5 || p->Nq[s] > kMaxAxis || p->Np[s] < np_lo || p->Np[s] > kMaxAxis) {
+      err = d.hermite ? "every q axis needs 5 <= N <= 48 points and every mode 2 <= Nh <= 48 Hermite functions"
+                      : "every axis needs 5 <= N <= 48 points";
       return false;
     }
-    if (!(p->Lq[s] > 0) || !(p->Lp[s] > 0) || !(p->m[s] > 0)) {
+    if (!(p->Lq[s] > 0) || (!d.hermite && !(p->Lp[s] > 0)) || !(p->m[s] > 0)) {
       err = "box half-widths and masses must be positive";
       return false;
     }
@@ -230,6 +272,7 @@ bool derive(const chfpe_params *p, Derived &d, std::string &err) {
     err = "one element must have fewer than 2^29 points";
     return false;
   }
+  if (d.hermite) return hcube_shape_ok(d, err);
   const PBShape ps = pblock_shape(d);
   if (ps.rows > kPBlockRPT * ps.RG) {
     if (pcube_shape_ok(d)) return true;  // k_pcube takes the p block
@@ -308,6 +351,10 @@ struct Launch {
   // passes are (q_2, q_3) and q_1 alone, and excitations need no qx)
   bool pcube = false, pcube_split = false, pcube_stream = false;
   PCube pcb{};
+  // Hermite basis: k_hcube over the q cube of each (branch, element, k)
+  bool hcube = false, hcube_split = false;
+  PCube hcb{};
+  int hcube_threads = 0, hcube_nb1 = 0;
   int pcube_threads = 0, pcube_nb1 = 0;
   size_t pcube_lds = 0;
   int qa_threads = 0, qf_threads = 0, qx_threads = 0;
@@ -421,7 +468,8 @@ void build_tables(chfpe_ctx *c, std::vector<double> &F, std::vector<double> &Vp,
     c->qgrid[s].resize(d.Nq[s]);
     c->pgrid[s].resize(d.Np[s]);
     for (int i = 0; i < d.Nq[s]; ++i) c->qgrid[s][i] = coord(i, d.Nq[s], p.Lq[s]);
-    for (int i = 0; i < d.Np[s]; ++i) c->pgrid[s][i] = coord(i, d.Np[s], p.Lp[s]);
+    // Hermite basis: no p grid (the p tables are unused; zeros)
+    for (int i = 0; i < d.Np[s]; ++i) c->pgrid[s][i] = d.hermite ? 0.0 : coord(i, d.Np[s], p.Lp[s]);
   }
   F.assign(3 * d.Q, 0.0);
   sq.assign(d.Q, 0.0);
@@ -477,6 +525,7 @@ void build_tables(chfpe_ctx *c, std::vector<double> &F, std::vector<double> &Vp,
     }
     sp[pi] = std::exp(-0.5 * p.beta * ke);
     wp[pi] = wgt * sp[pi];  // quadrature weight times the p part of exp(-beta H/2)
+    if (d.hermite) sp[pi] = wp[pi] = 1.0;  // p is integrated exactly: sum over k = 0 only
   }
   const int ne = d.ne;
   up.assign(3 * ne, -1);
@@ -532,17 +581,21 @@ void make_geom(chfpe_ctx *c) {
   }
   for (int s = 0; s < d.M; ++s) {
     const double hq = 2.0 * c->prm.Lq[s] / d.Nq[s];
-    const double hp = 2.0 * c->prm.Lp[s] / d.Np[s];
+    const double hp = d.hermite ? 0.0 : 2.0 * c->prm.Lp[s] / d.Np[s];
     g.bm[s] = c->prm.beta / (2.0 * c->prm.m[s]);
     g.dq_ca[s] = 7.0 / 9.0 / hq;
     g.dq_cb[s] = 1.0 / 36.0 / hq;
-    g.dp_ca[s] = 7.0 / 9.0 / hp;
-    g.dp_cb[s] = 1.0 / 36.0 / hp;
+    g.dp_ca[s] = d.hermite ? 0.0 : 7.0 / 9.0 / hp;
+    g.dp_cb[s] = d.hermite ? 0.0 : 1.0 / 36.0 / hp;
+    const double a = std::sqrt(2.0 * c->prm.m[s] / c->prm.beta);  // Hermite width a_s
+    g.ha[s] = a / (std::sqrt(2.0) * c->prm.m[s]);
+    g.hf[s] = 1.0 / (std::sqrt(2.0) * a);
+    g.hl[s] = std::sqrt(2.0) / a;
   }
-  // dV = prod h
+  // dV = prod h (q axes only in the Hermite basis: p is integrated exactly)
   c->dV = 1.0;
   for (int s = 0; s < d.M; ++s)
-    c->dV *= (2.0 * c->prm.Lq[s] / d.Nq[s]) * (2.0 * c->prm.Lp[s] / d.Np[s]);
+    c->dV *= (2.0 * c->prm.Lq[s] / d.Nq[s]) * (d.hermite ? 1.0 : 2.0 * c->prm.Lp[s] / d.Np[s]);
 }
 
 // Axis ids: 0..M-1 are q_1..q_M, M..2M-1 are p_1..p_M.
@@ -640,6 +693,22 @@ bool plan(chfpe_ctx *c) {
   const Derived &d = c->d;
   Launch &ln = c->ln;
   const int M = d.M;
+  if (d.hermite) {
+    // one k_hcube launch per stage; the grid tiles below are not used
+    ln.hcube = true;
+    PCube &h = ln.hcb;
+    h.N1 = d.Nq[0];
+    h.N2 = hcube_n2(d);
+    h.N3 = hcube_n3(d);
+    h.plane = h.N2 * h.N3;
+    h.rs = h.N3 + 1;
+    h.ntasks = d.ne * d.P;
+    h.nblk = pad8(h.ntasks);
+    ln.hcube_nb1 = nmax_bucket(h.N1);
+    ln.hcube_threads = (h.plane + 63) / 64 * 64;
+    ln.hcube_split = h.N1 == ln.hcube_nb1 && h.N2 == h.N1 && h.N3 == h.N1;
+    return true;
+  }
   const int NpM = d.Np[M - 1];
   // k_pblock: the innermost one (one mode) or two p axes
   PBlock &pb = ln.pb;
@@ -814,7 +883,7 @@ void allow_lds(K kern, size_t bytes) {
 struct Batch {
   Geom g;
   PBlock pb;
-  PCube pcb;
+  PCube pcb, hcb;
   QPass qa, qf, qx;
 };
 
@@ -828,6 +897,9 @@ Batch batch_of(const chfpe_ctx *c, int nb) {
   b.pcb = c->ln.pcb;
   b.pcb.ntasks *= nb;
   b.pcb.nblk = pad8(b.pcb.ntasks);
+  b.hcb = c->ln.hcb;
+  b.hcb.ntasks *= nb;
+  b.hcb.nblk = pad8(b.hcb.ntasks);
   QPass *q[3] = {&b.qa, &b.qf, &b.qx};
   const QPass *s[3] = {&c->ln.qa, &c->ln.qf, &c->ln.qx};
   for (int i = 0; i < 3; ++i) {
@@ -976,12 +1048,53 @@ void launch_q_t(chfpe_ctx *c, const Batch &b, const QPass &qp, int threads, size
 #undef CHFPE_QN
 }
 
+// Hermite basis: one k_hcube launch computes the right-hand side of X and
+// the stage update (EPI, coefficient cst) over every (branch, element, k).
+template <typename T, int NB1, bool SPLIT, int EPI>
+void launch_hcube_k(chfpe_ctx *c, const Batch &b, const T *X, const T *y, T *xo, double cst) {
+  const size_t lds = (kHCubeCF + 2 * (size_t)kHCubePL * b.hcb.N2 * b.hcb.rs) * sizeof(T);
+  auto kern = k_hcube<T, NB1, SPLIT, EPI>;
+  allow_lds(kern, lds);
+  hipLaunchKernelGGL(kern, dim3(b.hcb.nblk), dim3(c->ln.hcube_threads), lds, c->stream, b.g, c->tb, b.hcb, X, y,
+                     xo, cst);
+}
+
+template <typename T, int NB1, int EPI>
+void launch_hcube_n(chfpe_ctx *c, const Batch &b, const T *X, const T *y, T *xo, double cst) {
+  if constexpr (NB1 <= 24) {  // cubes of 32 or 48 points exceed the workgroup: never lane pairs
+    if (c->ln.hcube_split) {
+      launch_hcube_k<T, NB1, true, EPI>(c, b, X, y, xo, cst);
+      return;
+    }
+  }
+  launch_hcube_k<T, NB1, false, EPI>(c, b, X, y, xo, cst);
+}
+
+template <typename T, int EPI>
+void launch_hcube(chfpe_ctx *c, const Batch &b, const T *X, const T *y, T *xo, double cst) {
+  switch (c->ln.hcube_nb1) {
+    case 8: launch_hcube_n<T, 8, EPI>(c, b, X, y, xo, cst); break;
+    case 12: launch_hcube_n<T, 12, EPI>(c, b, X, y, xo, cst); break;
+    case 16: launch_hcube_n<T, 16, EPI>(c, b, X, y, xo, cst); break;
+    case 24: launch_hcube_n<T, 24, EPI>(c, b, X, y, xo, cst); break;
+    case 32: launch_hcube_n<T, 32, EPI>(c, b, X, y, xo, cst); break;
+    default: launch_hcube_n<T, 48, EPI>(c, b, X, y, xo, cst); break;
+  }
+}
+
 // One right-hand-side evaluation of X (t: partial right-hand side) fused with
 // the stage epilogue EPI (coefficient cst); all buffers hold b.g.nbatch
 // states.  kind: the timing kind of the stage-final launch.
 template <typename T, int EPI>
 void launch_stage(chfpe_ctx *c, const Batch &b, const T *X, T *t, const T *y, T *xo, double cst, int kind) {
   const Launch &ln = c->ln;
+  if (ln.hcube) {  // Hermite basis: the whole stage in one launch
+    const int hk = EPI == EPI_H1 ? K_HS1 : EPI == EPI_H4 ? K_HS4 : EPI == EPI_OUT ? K_HOUT
+                   : kind == K_QS3 ? K_HS3 : K_HS2;
+    TimedScope ts(c, hk, b.g.nbatch, sizeof(T));
+    launch_hcube<T, EPI>(c, b, X, y, xo, cst);
+    return;
+  }
   if (ln.pcube) {
     TimedScope ts(c, K_PCUBE, b.g.nbatch, sizeof(T));
     launch_pcube_t<T, T, false>(c, b, X, t, nullptr);
@@ -1011,6 +1124,10 @@ template <typename TO>
 void launch_perturb(chfpe_ctx *c, const double *W, TO *out, const double *grad) {
   TimedScope ts(c, K_PERTURB);
   const Batch b = batch_of(c, 1);
+  if (c->ln.hcube) {  // Hermite basis: a local raising of k, no derivative
+    hipLaunchKernelGGL((k_hperturb<TO>), dim3(2048), dim3(256), 0, c->stream, b.g, W, out, grad);
+    return;
+  }
   if (c->ln.pcube) {
     launch_pcube_t<double, TO, true>(c, b, W, out, grad);
     return;
@@ -1070,8 +1187,11 @@ int rk4(chfpe_ctx *c, double *yb, long long nsteps, double dt) {
 template <typename T>
 void observe_batch(chfpe_ctx *c, const T *W, int nb, double *dst, int dstride) {
   TimedScope ts(c, K_OBSERVE, nb, sizeof(T));
-  const int per = std::max(1, std::min(kPartials / nb, (int)((c->d.E + 255) / 256)));
-  hipLaunchKernelGGL((k_reduce_w0<T>), dim3(per, nb), dim3(256), 0, c->stream, W, c->Cw, c->wp, c->d.Q, c->d.P,
+  // element 0 of the grid basis: every (q, p); Hermite basis: the k = 0 slice,
+  // the first Q values (p integrated exactly)
+  const int P = c->d.hermite ? 1 : c->d.P;
+  const int per = std::max(1, std::min(kPartials / nb, (int)(((long long)c->d.Q * P + 255) / 256)));
+  hipLaunchKernelGGL((k_reduce_w0<T>), dim3(per, nb), dim3(256), 0, c->stream, W, c->Cw, c->wp, c->d.Q, P,
                      c->partial, (long long)c->d.S);
   hipLaunchKernelGGL(k_reduce_final, dim3(nb), dim3(256), 0, c->stream, c->partial, per, c->dV, dst, dstride);
 }
@@ -1576,20 +1696,22 @@ int chfpe_equilibrate(chfpe_ctx *c, int64_t n_steps, double dt) {
   if (n_steps < 0 || !std::isfinite(dt) || (n_steps > 0 && !(dt > 0)))
     return fail(c, CHFPE_EINVAL, "need n_steps >= 0 and dt > 0");
   const int nb = 1024;
+  // Hermite basis: c_{0,0} = e^{-beta U/2} / Z_q in the first Q values (a unit p block)
+  const int P = c->d.hermite ? 1 : c->d.P;
   hipLaunchKernelGGL((k_boltzmann<double>), dim3(nb), dim3(256), 0, c->stream, c->y, c->sq, c->sp, c->d.Q,
-                     c->d.P, c->d.S);
+                     P, c->d.S);
   // Z = dV sum w exp(-beta H) = dV sum (w_q sq)(w_p sp) h_0 with h_0 = sq sp
   std::vector<double> ones(c->d.Q);
   for (int ql = 0; ql < c->d.Q; ++ql) ones[ql] = c->wq_host[ql] * c->sq_host[ql];
   HIPCHK(c, hipMemcpyAsync(c->Cw, ones.data(), ones.size() * sizeof(double), hipMemcpyHostToDevice,
                            c->stream));
   {
-    const int nbr = std::min(kPartials, std::max(1, (int)((c->d.E + 255) / 256)));
+    const int nbr = std::min(kPartials, std::max(1, (int)(((long long)c->d.Q * P + 255) / 256)));
     hipLaunchKernelGGL((k_reduce_w0<double>), dim3(nbr), dim3(256), 0, c->stream, c->y, c->Cw, c->wp,
-                       c->d.Q, c->d.P, c->partial, (long long)c->d.S);
+                       c->d.Q, P, c->partial, (long long)c->d.S);
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, c->stream, c->partial, nbr, 1.0, c->scal, 1);
     hipLaunchKernelGGL((k_normalise<double>), dim3(1024), dim3(256), 0, c->stream, c->y, c->scal, c->dV,
-                       (int)c->d.E);
+                       c->d.Q * P);
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));  // `ones` is read by the async copy
   int rc = rk4(c, c->y, n_steps, dt);
@@ -1793,10 +1915,12 @@ int64_t chfpe_state_count(const chfpe_ctx *c) { return c ? c->d.S : 0; }
 
 int chfpe_get_state(chfpe_ctx *c, double *host) {
   if (!c || !host) return CHFPE_EINVAL;
-  // W = exp(-beta H/2) h, converted in a scratch buffer
+  // W = exp(-beta H/2) h, converted in a scratch buffer (the Hermite
+  // coefficients are copied as they are)
   HIPCHK(c, hipMemcpyAsync(c->xb, c->y, c->d.S * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  hipLaunchKernelGGL((k_sym_scale<double>), dim3(1024), dim3(256), 0, c->stream, c->xb, c->sq, c->sp, c->d.Q,
-                     c->d.P, c->d.S, 1);
+  if (!c->d.hermite)
+    hipLaunchKernelGGL((k_sym_scale<double>), dim3(1024), dim3(256), 0, c->stream, c->xb, c->sq, c->sp, c->d.Q,
+                       c->d.P, c->d.S, 1);
   HIPCHK(c, hipMemcpyAsync(host, c->xb, c->d.S * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return last_launch_error(c);
@@ -1805,8 +1929,9 @@ int chfpe_get_state(chfpe_ctx *c, double *host) {
 int chfpe_set_state(chfpe_ctx *c, const double *host) {
   if (!c || !host) return CHFPE_EINVAL;
   HIPCHK(c, hipMemcpyAsync(c->y, host, c->d.S * sizeof(double), hipMemcpyHostToDevice, c->stream));
-  hipLaunchKernelGGL((k_sym_scale<double>), dim3(1024), dim3(256), 0, c->stream, c->y, c->sq, c->sp, c->d.Q,
-                     c->d.P, c->d.S, 0);
+  if (!c->d.hermite)
+    hipLaunchKernelGGL((k_sym_scale<double>), dim3(1024), dim3(256), 0, c->stream, c->y, c->sq, c->sp, c->d.Q,
+                       c->d.P, c->d.S, 0);
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return last_launch_error(c);
 }
@@ -1946,6 +2071,7 @@ int chfpe_set_kernel_timing(chfpe_ctx *c, int32_t every) {
 int chfpe_autotune(chfpe_ctx *c, int32_t n_steps) {
   if (!c) return CHFPE_EINVAL;
   if (n_steps < 1 || n_steps > 1000) return fail(c, CHFPE_EINVAL, "need 1 <= n_steps <= 1000");
+  if (c->d.hermite) return CHFPE_OK;  // one k_hcube shape: nothing to choose
   const Derived &d = c->d;
   // the timed steps run on scratch buffers holding zeros (the work does not
   // depend on the values); the cached wave graph holds the old tile shapes
@@ -2099,6 +2225,7 @@ int chfpe_closure_features(const chfpe_params *p, float *feat, int32_t *axis_of_
 
 int chfpe_closure_moments(chfpe_ctx *c, double *G, double *b, double *ct) {
   if (!c || !G || !b || !ct) return CHFPE_EINVAL;
+  if (c->d.hermite) return fail(c, CHFPE_EINVAL, "the closure is defined for the grid basis only");
   const Derived &d = c->d;
   const int M = d.M, nd = 2 * M;
   int Nf[6], Nc[6];
@@ -2281,6 +2408,7 @@ int chfpe_set_closure(chfpe_ctx *c, const double *sv) {
     c->closure_on = false;
   } else {
     const Derived &d = c->d;
+    if (d.hermite) return fail(c, CHFPE_EINVAL, "the closure is defined for the grid basis only");
     if (d.prec != CHFPE_FP64) return fail(c, CHFPE_EINVAL, "the closure runs with FP64 states only");
     const int M = d.M;
     int N[6];

@@ -370,6 +370,9 @@ struct Geom {
   double dq_ca[3], dq_cb[3];  // 7/(9 h), 1/(36 h) for q_s
   double dp_ca[3], dp_cb[3];  // same for p_s
   double bm[3];               // beta / (2 m_s)
+  // Hermite basis in p (a_s = sqrt(2 m_s / beta)): a_s / (sqrt(2) m_s),
+  // 1 / (sqrt(2) a_s) and sqrt(2) / a_s
+  double ha[3], hf[3], hl[3];
 };
 
 struct Tabs {
@@ -1475,6 +1478,262 @@ k_stream_copy(uint4 *__restrict__ dst, const uint4 *__restrict__ src, const long
     dst[i + 3 * st] = d;
   }
   for (; i < n16; i += st) dst[i] = src[i];
+}
+
+
+// ---------------------------------------------------------------------------
+// Hermite basis in p: k_hcube, k_hperturb
+// ---------------------------------------------------------------------------
+// The paper's own discretisation (Sec. III A; Appendix A, Eq. (HEOM2FP-H))
+// expands each element in Hermite functions of the momenta,
+//   W_n = e^{-beta U/2} prod_s psi_0(p_s) sum_k c_{n,k}(q) prod_s psi_{k_s}(p_s),
+// so a state is c[branch][n][k_1..k_M][q_1..q_M] on the q grid alone (k_s <
+// Nh_s, held in Np[s]).  With a_s = sqrt(2 m_s / beta) the equation reads
+//   dc_{n,k}/dt = - sum_s n_s gamma_s c_{n,k}
+//     + sum_s F_s(q) / (sqrt2 a_s) (sqrt(k_s+1) c_{n,k+e_s} - sqrt(k_s) c_{n,k-e_s})
+//     + sum_s D_{q_s} [ -a_s / (sqrt2 m_s) (sqrt(k_s+1) c_{n,k+e_s} + sqrt(k_s) c_{n,k-e_s}) ]
+//     - sum_s sqrt2 / a_s sqrt(k_s) V_s'(q_s) c_{n+e_s,k-e_s}
+//     + sum_s n_s zeta_s gamma_s (m_s/beta) sqrt2 / a_s sqrt(k_s+1) V_s'(q_s) c_{n-e_s,k+e_s}
+// (the appendix's D^{+-}, Theta and Phi written out), and the only
+// derivatives left are the compact ones along q.  That is the structure of
+// k_pcube_s with p and q exchanged: a task is one (branch, element, Hermite
+// index k) and its block is the whole q cube, contiguous; the fields of the
+// q_2 and q_3 derivatives mix the Hermite neighbours k +- e_s of the same
+// element, and the q_1 derivative is folded into one sweep over the q_1
+// planes (t = A^{-1} (A s + B G_1), as in k_pcube_s).  Because one task sees
+// every derivative of its block, the RK4 stage update is fused in: a whole
+// stage is one launch (EPI_OUT writes the right-hand side itself).
+// Missing neighbours (k_s at either end of the truncation, n +- e_s outside
+// the hierarchy) point at the task's own block with zero factors.
+
+// Largest workgroup for a q_1 bucket (the q_1 line and a round's loads in
+// registers).
+template <typename T, int NB1>
+constexpr int hcube_max_threads() {
+  return NB1 >= 48 ? 256 : NB1 >= 32 ? 512 : NB1 >= 24 ? 768 : 1024;
+}
+// Task constants of k_hcube in LDS: per mode s (slot s of each group of
+// three) the factors of c_{k+e_s} and c_{k-e_s} in the q-derivative field
+// (GU, GD) and in the force term (FU, FD), of c_{n+e_s,k-e_s} (PH) and
+// c_{n-e_s,k+e_s} (TH); then the damping and V_2', V_3' on their grids.
+constexpr int kHcGU = 0, kHcGD = 3, kHcFU = 6, kHcFD = 9, kHcPH = 12, kHcTH = 15, kHcDamp = 18;
+constexpr int kHcV2 = 20, kHcV3 = kHcV2 + kTab;
+constexpr int kHCubeCF = kHcV3 + kTab;
+constexpr int kHCubePL = 2;  // q_1 planes per round
+
+template <typename T, int NB1, bool SPLIT, int EPI>
+__global__ void __launch_bounds__((hcube_max_threads<T, NB1>()))
+k_hcube(const Geom g, const Tabs tb, const PCube pc, const T *__restrict__ X, const T *__restrict__ y,
+        T *__restrict__ out, const double cst) {
+  constexpr int PL = kHCubePL;
+  constexpr int NR = (NB1 + PL - 1) / PL;
+  constexpr int RC = 2;  // stencil reach along q_1
+  constexpr T third = T(1.0 / 3.0);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int task = xcd_task(blockIdx.x, pc.nblk);
+  if (task >= pc.ntasks) return;
+  const int N1 = SPLIT ? NB1 : pc.N1, N2 = SPLIT ? NB1 : pc.N2, N3 = SPLIT ? NB1 : pc.N3;
+  const int plane = SPLIT ? NB1 * NB1 : pc.plane;
+  const int rs = SPLIT ? NB1 + 1 : pc.rs;
+  T *CF = reinterpret_cast<T *>(smem_raw);
+  T *G2 = CF + kHCubeCF;  // [PL][N2][rs]
+  T *G3 = G2 + PL * N2 * rs;
+  const int ne_all = g.ne * g.nbatch;
+  const int ea = task % ne_all;  // (branch, element) fastest: the elements of one k are adjacent tasks
+  const int kl = task / ne_all;  // Hermite multi-index, k_M fastest
+  const int br = ea / g.ne;
+  const int e = ea - br * g.ne;
+  const int tid = threadIdx.x;
+  const bool own = tid < plane;
+  const int j2 = own ? tid / N3 : 0;
+  const int j3 = own ? tid - j2 * N3 : 0;
+  const long long Q = g.Q;
+  const long long slice = ((long long)ea * g.P + kl) * Q;  // this task's q cube
+  const T *Xe = X + slice;
+  T *Oe = out + slice;
+  const T *Ye = EPI == EPI_H2 ? y + slice : nullptr;
+  const T *Xb = X + (long long)br * g.ne * g.E;  // this branch's element 0
+  int kk[3];
+  {
+    int rem = kl;
+    for (int s = 2; s >= 0; --s) {
+      kk[s] = s < g.M ? rem % g.Np[s] : 0;
+      rem = s < g.M ? rem / g.Np[s] : rem;
+    }
+  }
+  const T *Xu[3], *Xd[3], *Hu[3], *Hd[3];  // c_{k+e}, c_{k-e}, c_{n+e,k-e}, c_{n-e,k+e}
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const bool on = s < g.M;
+    const bool kup = on && kk[s] + 1 < g.Np[s];
+    const bool kdn = on && kk[s] > 0;
+    const int up = on ? tb.up[e * 3 + s] : -1;
+    const int dn = on ? tb.dn[e * 3 + s] : -1;
+    const long long ks = on ? (long long)g.PS[s] * Q : 0;
+    Xu[s] = kup ? Xe + ks : Xe;
+    Xd[s] = kdn ? Xe - ks : Xe;
+    Hu[s] = (kdn && up >= 0) ? Xb + ((long long)up * g.P + kl) * Q - ks : Xe;
+    Hd[s] = (kup && dn >= 0) ? Xb + ((long long)dn * g.P + kl) * Q + ks : Xe;
+  }
+  if (tid < 3) {
+    const int s = tid;
+    const bool on = s < g.M;
+    const bool kup = on && kk[s] + 1 < g.Np[s];
+    const bool kdn = on && kk[s] > 0;
+    const double sp = kup ? sqrt((double)(kk[s] + 1)) : 0.0;  // zero past the truncation
+    const double sm = kdn ? sqrt((double)kk[s]) : 0.0;
+    const int up = on ? tb.up[e * 3 + s] : -1;
+    CF[kHcGU + s] = T(-g.ha[s] * sp);
+    CF[kHcGD + s] = T(-g.ha[s] * sm);
+    CF[kHcFU + s] = T(g.hf[s] * sp);
+    CF[kHcFD + s] = T(-g.hf[s] * sm);
+    CF[kHcPH + s] = T(up >= 0 ? -g.hl[s] * sm : 0.0);
+    CF[kHcTH + s] = T(on ? tb.cc[e * 3 + s] * g.hl[s] * sp : 0.0);  // cc is zero when n_s = 0
+    if (s == 0) CF[kHcDamp] = T(tb.damp[e]);
+  }
+  if (tid < N2) CF[kHcV2 + tid] = T(g.M > 1 ? tb.Vp[1 * kTab + tid] : 0.0);
+  if (tid < N3) CF[kHcV3 + tid] = T(g.M > 2 ? tb.Vp[2 * kTab + tid] : 0.0);
+  __syncthreads();
+  const T ca1 = T(g.dq_ca[0]), cb1 = T(g.dq_cb[0]);
+  const uint32_t own_off = (uint32_t)(own ? tid : 0);
+  const double *F2 = tb.F + 1 * Q, *F3 = tb.F + 2 * Q;
+
+  T ln[NB1];  // row j of A t = r while it collects its terms, then its forward result d_j
+#pragma unroll
+  for (int j = 0; j < NB1; ++j) ln[j] = T(0);
+  T dprev = T(0);
+  auto elim = [&](const int j) {
+    const T d = j == 0 ? ln[j] : fma_t(T(-kThomas.inv[j] / 3.0), dprev, ln[j] * T(kThomas.inv[j]));
+    dprev = d;
+    ln[j] = d;
+  };
+
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int i0 = r * PL;
+    if (i0 >= N1) break;  // uniform
+    T sv[PL], gv[PL];
+#pragma unroll
+    for (int k = 0; k < PL; ++k) {
+      const int i = i0 + k;
+      sv[k] = gv[k] = T(0);
+      if (i < N1) {
+        uint32_t o = (uint32_t)(i * plane) + own_off;
+        asm volatile("" : "+v"(o));
+        const T c0 = at_u32(Xe, o);
+        const T u1 = at_u32(Xu[0], o), d1 = at_u32(Xd[0], o);
+        const T u2 = at_u32(Xu[1], o), d2 = at_u32(Xd[1], o);
+        const T u3 = at_u32(Xu[2], o), d3 = at_u32(Xd[2], o);
+        const T a1 = at_u32(Hu[0], o), b1 = at_u32(Hd[0], o);
+        const T a2 = at_u32(Hu[1], o), b2 = at_u32(Hd[1], o);
+        const T a3 = at_u32(Hu[2], o), b3 = at_u32(Hd[2], o);
+        const T f1 = T(at_u32(tb.F, o)), f2 = T(at_u32(F2, o)), f3 = T(at_u32(F3, o));
+        const T v1 = T(tb.Vp[0 * kTab + i]), v2 = CF[kHcV2 + j2], v3 = CF[kHcV3 + j3];
+        sv[k] = -CF[kHcDamp] * c0 + f1 * (CF[kHcFU] * u1 + CF[kHcFD] * d1) +
+                f2 * (CF[kHcFU + 1] * u2 + CF[kHcFD + 1] * d2) + f3 * (CF[kHcFU + 2] * u3 + CF[kHcFD + 2] * d3) +
+                v1 * (CF[kHcPH] * a1 + CF[kHcTH] * b1) + v2 * (CF[kHcPH + 1] * a2 + CF[kHcTH + 1] * b2) +
+                v3 * (CF[kHcPH + 2] * a3 + CF[kHcTH + 2] * b3);
+        gv[k] = CF[kHcGU] * u1 + CF[kHcGD] * d1;
+        if (own) {
+          const int li = (k * N2 + j2) * rs + j3;
+          G2[li] = CF[kHcGU + 1] * u2 + CF[kHcGD + 1] * d2;
+          G3[li] = CF[kHcGU + 2] * u3 + CF[kHcGD + 2] * d3;
+        }
+      }
+      asm volatile("" : "+v"(sv[k]), "+v"(gv[k]));
+    }
+    __syncthreads();
+    // q_2 lines of G2 (fixed k, j3) and q_3 lines of G3 (fixed k, j2)
+    const int npl = min(PL, N1 - i0);
+    const int nl2 = npl * N3, nl = nl2 + npl * N2;
+    if (SPLIT) {
+#pragma unroll 1
+      for (int hl = tid; hl < 2 * nl; hl += blockDim.x) {
+        const int l = hl >> 1;
+        if (l < nl2) {
+          const int k = l / N3, c = l - k * N3;
+          compact_split<T, NB1>(G2, k * N2 * rs + c, rs, hl & 1, T(g.dq_ca[1]), T(g.dq_cb[1]));
+        } else {
+          compact_split<T, NB1>(G3, (l - nl2) * rs, 1, hl & 1, T(g.dq_ca[2]), T(g.dq_cb[2]));
+        }
+      }
+    } else {
+#pragma unroll 1
+      for (int l = tid; l < nl; l += blockDim.x) {
+        if (l < nl2) {
+          const int k = l / N3, c = l - k * N3;
+          compact_lds<T>(G2, k * N2 * rs + c, rs, N2, T(g.dq_ca[1]), T(g.dq_cb[1]));
+        } else {
+          compact_lds<T>(G3, (l - nl2) * rs, 1, N3, T(g.dq_ca[2]), T(g.dq_cb[2]));
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PL; ++k) {
+      const int i = i0 + k;
+      if (i < N1) {
+        const int li = (k * N2 + j2) * rs + j3;
+        const T s = sv[k] + G2[li] + G3[li];
+        const T gg = gv[k];
+        ln[i] += s;  // A s
+        if (i >= 1) ln[i >= 1 ? i - 1 : 0] += third * s;
+        if (i + 1 < NB1) ln[i + 1 < NB1 ? i + 1 : 0] += third * s;
+        // B G_1: row j takes ca (G_{j+1} - G_{j-1}) + cb (G_{j+2} - G_{j-2})
+        if (i >= 1) ln[i >= 1 ? i - 1 : 0] += ca1 * gg;
+        if (i >= 2) ln[i >= 2 ? i - 2 : 0] += cb1 * gg;
+        if (i + 1 < NB1) ln[i + 1 < NB1 ? i + 1 : 0] -= ca1 * gg;
+        if (i + 2 < NB1) ln[i + 2 < NB1 ? i + 2 : 0] -= cb1 * gg;
+        if (i >= RC) elim(i >= RC ? i - RC : 0);
+        if (i == N1 - 1) {
+#pragma unroll
+          for (int q = RC - 1; q >= 0; --q)
+            if (i - q >= 0) elim(i - q >= 0 ? i - q : 0);
+        }
+      }
+    }
+    __syncthreads();  // the next round overwrites the planes
+  }
+  if (!own) return;
+  // back substitution from the far end of the q_1 line, with the stage update
+  T x = T(0);
+#pragma unroll
+  for (int j = NB1 - 1; j >= 0; --j) {
+    if (j < N1) {
+      x = ln[j] - T(kThomas.cp[j]) * x;
+      uint32_t o = (uint32_t)(j * plane + tid);
+      asm volatile("" : "+v"(o));
+      if (EPI == EPI_OUT)
+        at_u32(Oe, o) = x;
+      else if (EPI == EPI_H1)
+        at_u32(Oe, o) = at_u32(Xe, o) + T(cst) * x;
+      else if (EPI == EPI_H2)
+        at_u32(Oe, o) = at_u32(Ye, o) + T(cst) * x;
+      else
+        at_u32(Oe, o) = at_u32(Oe, o) + T(cst) * x;
+    }
+  }
+}
+
+// Excitation in the Hermite basis, Eq. (Opticalexc): dX/dq_s d/dp_s acts on
+// W = e^{-beta H/2} h as dX/dq_s (d/dp_s - p_s / a_s^2) on h, which raises
+// the Hermite index: (X^x c)_{n,k} = - sum_s dX/dq_s(q) sqrt2 / a_s sqrt(k_s)
+// c_{n,k-e_s}, for every element n (grad[s][q] = dX/dq_s; one state).
+template <typename TO>
+__global__ void __launch_bounds__(256)
+k_hperturb(const Geom g, const double *__restrict__ W, TO *__restrict__ out, const double *__restrict__ grad) {
+  const long long Q = g.Q, S = (long long)g.ne * g.E;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < S; i += (long long)gridDim.x * 256) {
+    const long long sl = i / Q;  // (element, Hermite index)
+    const int ql = (int)(i - sl * Q);
+    const int kl = (int)(sl % g.P);
+    double v = 0.0;
+    for (int s = 0; s < g.M; ++s) {
+      const int ks = (kl / g.PS[s]) % g.Np[s];
+      if (ks > 0) v -= grad[s * Q + ql] * g.hl[s] * sqrt((double)ks) * W[i - (long long)g.PS[s] * Q];
+    }
+    out[i] = TO(v);
+  }
 }
 
 }  // namespace chfpe

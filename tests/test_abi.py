@@ -141,3 +141,26 @@ def test_batch_beyond_one_dispatch_is_rejected(binding):
     ctx = ctypes.c_void_p()
     assert L.chfpe_setup(ctypes.byref(p), None, 0, None, ctypes.byref(ctx)) == binding.CHFPE_EINVAL
     assert b"dispatch" in L.chfpe_last_error(None)
+
+
+def test_hermite_basis_limits(binding):
+    """The Hermite basis (CHFPE_BASIS_HERMITE): Np counts Hermite functions
+    (2..48 per mode; Lp is not read), the state is ne x prod(Nh) x prod(Nq),
+    and the q cube of one task must fit one workgroup."""
+    w = wl.workload("three_mode_24_hermite")
+    p = binding.params_from_workload(w)
+    assert p.basis == binding.CHFPE_BASIS_HERMITE
+    n = binding.workspace_bytes(p)
+    assert n >= 6 * 8 * 10 * 12 ** 3 * 24 ** 3
+    p.Lp[0] = -1.0  # not read in the Hermite basis
+    assert binding.workspace_bytes(p) == n
+    for Nh, ok in ((1, False), (2, True), (48, True), (49, False)):
+        q = binding.params_from_workload(wl.workload("two_mode_32_hermite", Np=[Nh, 3]))
+        assert (binding.workspace_bytes(q) > 0) == ok, Nh
+    # q_1 lines of 24 points allow 768 threads: a 24 x 32 plane (768) fits, 32 x 32 does not
+    for Nq, ok in (([24, 24, 32], True), ([24, 32, 32], False), ([32, 16, 16], True), ([32, 24, 24], False)):
+        q = binding.params_from_workload(wl.workload("three_mode_24_hermite", Nq=Nq, Np=[3, 3, 3]))
+        assert (binding.workspace_bytes(q) > 0) == ok, Nq
+    bad = binding.params_from_workload(w)
+    bad.basis = 7
+    assert binding.workspace_bytes(bad) == 0

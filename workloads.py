@@ -102,6 +102,20 @@ def _make_workloads() -> dict:
     w["Np"] = [12] * 3
     w.update(precision="f32")
     out["three_mode_12"] = w
+
+    # The three-mode model with the paper's own p discretisation (Hermite
+    # functions, Sec. III A): the 24^3 q grid and 12 Hermite functions per
+    # mode (Np counts them; Lp is not used).
+    w = copy.deepcopy(out["three_mode_24"])
+    w["Np"] = [12] * 3
+    w.update(basis="hermite")
+    out["three_mode_24_hermite"] = w
+
+    # The two-mode model in the Hermite basis: 32^2 q grid, 16 functions per mode.
+    w = copy.deepcopy(out["two_mode_32"])
+    w["Np"] = [16] * 2
+    w.update(basis="hermite")
+    out["two_mode_32_hermite"] = w
     return out
 
 
