@@ -75,7 +75,7 @@ def rk4_steps(w) -> int:
 
 # Bench-step slices (equilibration steps, t1 columns, t2 samples) of jobs too
 # long to run whole per step; other workloads run their whole job.
-SLICES = {"three_mode_24": (16, 2, 8)}
+SLICES = {"three_mode_24": (16, 2, 8), "three_mode_24_hermite": (64, 8, 32)}
 
 
 def job_slice(w, name: str, spec: str):
@@ -96,7 +96,12 @@ def describe(name: str, w) -> str:
     same = len(set(list(w["Nq"]) + list(w["Np"]))) == 1
     if same:
         grid = f"{w['Nq'][0]}^{2 * M}"
-    return (f"{name}: {M} mode{'s' if M > 1 else ''}, {grid} (q,p) grid, depth {w['K']}; "
+    if w.get("basis") == "hermite":
+        grid = ("x".join(str(n) for n in w["Nq"]) + " q grid x " + "x".join(str(n) for n in w["Np"]) +
+                " Hermite functions in p (Sec. III A)")
+    else:
+        grid += " (q,p) grid"
+    return (f"{name}: {M} mode{'s' if M > 1 else ''}, {grid}, depth {w['K']}; "
             f"job = equilibration {w['eq_steps']} + 2D THz-Raman {w['n_t1']} t1 x {w['n_t2']} t2 samples "
             f"(stride {w['stride1']}, dt {w['dt']}) = {rk4_steps(w)} RK4 steps")
 
@@ -206,6 +211,8 @@ def one_thread_rate(name: str):
 
 # k_qpass epilogues; the two middle RK4 stages share one instantiation
 _EPI_KIND = {0: "qpass_acc", 1: "qpass_out", 2: "qpass_rk4_s1", 3: "qpass_rk4_s23", 4: "qpass_rk4_s4"}
+# k_hcube (Hermite basis): one launch per stage, same epilogue numbering
+_HEPI_KIND = {1: "hcube_out", 2: "hcube_rk4_s1", 3: "hcube_rk4_s23", 4: "hcube_rk4_s4"}
 
 
 def _short_name(name: str) -> str:
@@ -228,6 +235,10 @@ def _kind_of(short: str, grid: int, min_grid: dict):
             kind = "perturb_q"
         else:
             kind = _EPI_KIND[int(targs[4])]
+    elif fam == "k_hcube":
+        kind = _HEPI_KIND[int(targs[3])]  # <T, NB1, SPLIT, EPI>
+    elif fam == "k_hperturb":
+        kind = "perturb"
     elif fam == "k_reduce_w0":
         kind = "observe"
     else:
@@ -307,7 +318,7 @@ def summarise_counters(args, kern_cmd: str) -> None:
         passes.append(names)
         for r in rows:
             s = _short_name(r["Kernel_Name"])
-            if not (s.startswith("k_pcube") or s.startswith("k_qpass") or s.startswith("k_pblock")):
+            if not s.startswith(("k_pcube", "k_qpass", "k_pblock", "k_hcube")):
                 continue
             key = (s, _grid(r))
             per.setdefault(key, {})
@@ -453,7 +464,7 @@ def summarise(args) -> int:
                   "|---|---|---|---|---|---|---|"]
         for kind in rec["bytes_per_launch"]:
             # the two middle RK4 stages share one instantiation (qpass_rk4_s23)
-            a = alg.get(kind) or (alg.get("qpass_rk4_s2") if kind == "qpass_rk4_s23" else None)
+            a = alg.get(kind) or (alg.get(kind[:-3] + "s2") if kind.endswith("_rk4_s23") else None)
             t = rec["bytes_per_launch"][kind]
             lines.append(f"| {kind} | {per[kind]['fetch'][0]} | {rec['fetch_bytes_per_launch'][kind] / 1e6:.2f} | "
                          f"{rec['write_bytes_per_launch'][kind] / 1e6:.2f} | {t / 1e6:.2f} | "
@@ -504,7 +515,8 @@ def main(argv=None):
                     help="NB,SPLIT,PC[,RUN]: fixed tile shapes (k_pblock blocks per task, lane-pair "
                          "line solves 0/1, q-pass run positions per tile, k_pblock block groups "
                          "per state in task order) instead of autotuning")
-    ap.add_argument("--mode", choices=["bench", "kernels", "rk4", "summarise", "precision", "closure", "oracle1"],
+    ap.add_argument("--mode", choices=["bench", "kernels", "rk4", "summarise", "precision", "closure", "oracle1",
+                                       "basis"],
                     default="bench",
                     help="kernels: a few RK4 steps of the workload (single state, then one "
                          "batched wave) plus a plain copy of known size, for hardware-counter "
@@ -544,6 +556,13 @@ def main(argv=None):
     ap.add_argument("--traffic-variant", action="store_true",
                     help="summarise: write only a tile-specific traffic record (traffic_<workload>_tiles_<tiles>.json)")
     ap.add_argument("--rk4-steps", type=int, default=4, help="RK4 steps in --mode kernels")
+    ap.add_argument("--basis-run", default="400,4,32",
+                    help="basis: EQ,N_T1,N_T2 of the R^(2) both p bases compute (strides 1, the workload's dt)")
+    ap.add_argument("--hermite-n", type=int, default=0,
+                    help="basis: Hermite functions per mode (0: those of the workload's _hermite variant)")
+    ap.add_argument("--basis-ref", type=int, default=0,
+                    help="basis: also a reference run with this many Hermite functions per mode, "
+                         "against which both bases' errors are reported (0: none)")
     ap.add_argument("--tune", action="store_true", help="rk4: autotune the tile shapes first")
     args = ap.parse_args(argv)
     if args.mode == "summarise":
@@ -586,7 +605,7 @@ def main(argv=None):
         args.batch = 1  # propagation of one FP64 state: no branch buffers
     elif args.batch <= 0:
         args.batch = auto_batch(pk, w, prec, torch.cuda.get_device_properties(0).total_memory)
-    if args.mode in ("precision", "closure"):
+    if args.mode in ("precision", "closure", "basis"):
         # these modes make their own contexts; no workspace of this shape
         S = wl.n_elements(int(w["M"]), int(w["K"])) * int(np.prod(w["Nq"])) * int(np.prod(w["Np"]))
 
@@ -756,6 +775,49 @@ def main(argv=None):
                "lr": args.closure_lr, "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
                "data_s": t_data, "train_s": t_train, "judge": [j_eq, j1, j2, js], "cases": rows,
                "speedup_closure_vs_fine": float(np.mean([r["fine_s"] / r["closure_s"] for r in rows]))}
+        print(json.dumps(out), flush=True)
+        return 0
+
+    if args.mode == "basis":
+        # the same R^(2) in both p bases on the workload's q grid (FP64): the
+        # p grid of the workload and the Hermite functions of Sec. III A
+        import copy
+        n_eq, n1, n2 = (int(x) for x in args.basis_run.split(","))
+        wh = copy.deepcopy(w)
+        nh = args.hermite_n or int(wl.workload(args.workload + "_hermite")["Np"][0])
+        wh["Np"] = [nh] * int(w["M"])
+        wh["basis"] = "hermite"
+        res = {}
+        runs = [("grid", w), ("hermite", wh)]
+        if args.basis_ref:
+            wr = copy.deepcopy(wh)
+            wr["Np"] = [args.basis_ref] * int(w["M"])
+            runs.append(("reference", wr))
+        for name, ww in runs:
+            with pk.Solver(pk.params_from_workload(ww, precision=pk.CHFPE_FP64, batch=1)) as sv:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                sv.equilibrate(n_eq, dt)
+                R = sv.response_2d(w["A"], w["B"], w["C"], n1, n2, 1, 1, dt)
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+                steps = n_eq + (n1 - 1) + n1 * (n2 - 1)
+                res[name] = {"seconds": el, "values_per_state": sv.count, "R": R,
+                             "updates_per_s": sv.count * steps / el}
+            log(f"[basis] {name}: {el:.2f} s, {res[name]['values_per_state']} values per state")
+        Rg, Rh = res["grid"]["R"], res["hermite"]["R"]
+        out = {"mode": "basis", "workload": args.workload, "q_grid": w["Nq"], "p_grid": w["Np"], "p_box": w["Lp"],
+               "hermite_functions": wh["Np"], "run": {"eq_steps": n_eq, "n_t1": n1, "n_t2": n2, "dt": dt},
+               "R_rel_l2_hermite_vs_grid": float(np.linalg.norm(Rh - Rg) / np.linalg.norm(Rg)),
+               "R_max_abs_grid": float(np.abs(Rg).max()),
+               "speedup_hermite_over_grid": res["grid"]["seconds"] / res["hermite"]["seconds"]}
+        if args.basis_ref:
+            Rr = res["reference"]["R"]
+            out["reference_hermite_functions"] = [args.basis_ref] * int(w["M"])
+            out["R_rel_l2_vs_reference"] = {k: float(np.linalg.norm(res[k]["R"] - Rr) / np.linalg.norm(Rr))
+                                            for k in ("grid", "hermite")}
+        for name in res:
+            out[name] = {k: v for k, v in res[name].items() if k != "R"}
         print(json.dumps(out), flush=True)
         return 0
 
