@@ -263,6 +263,26 @@ def response_2d(w: dict, A: dict, B: dict, Cop: dict, Ceq, n_t1: int, n_t2: int,
     return R
 
 
+def response_3d(w: dict, A: dict, B: dict, Cop: dict, D: dict, Ceq, n_t1: int, t2_steps: int, n_t3: int,
+                stride1: int, stride3: int, dt: float, T=None) -> np.ndarray:
+    """R^(3)[j3, j1] of Eq. (3Dresponse) at the waiting time t2 = t2_steps dt
+    (t1 fastest): each t1 branch follows B^x, the waiting time, C^x and the
+    t3 samples of <D>."""
+    T = tables(w) if T is None else T
+    R = np.empty((int(n_t3), int(n_t1)))
+    u = perturb(w, A, Ceq)
+    for j1 in range(int(n_t1)):
+        if j1 > 0:
+            u = rk4(w, u, stride1, dt, T)
+        v = rk4(w, perturb(w, B, u), t2_steps, dt, T)
+        x = perturb(w, Cop, v)
+        for j3 in range(int(n_t3)):
+            if j3 > 0:
+                x = rk4(w, x, stride3, dt, T)
+            R[j3, j1] = observe(w, D, x, T)
+    return R
+
+
 def hermite_functions(kmax: int, p: np.ndarray, a: float) -> np.ndarray:
     """psi_0..psi_{kmax-1} at the points p (rows), by the three-term recurrence
     psi_{j+1} = sqrt(2/(j+1)) (p/a) psi_j - sqrt(j/(j+1)) psi_{j-1}."""

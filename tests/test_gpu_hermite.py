@@ -161,3 +161,46 @@ def test_hermite_workload_shape_is_accepted_and_planned(pk):
         s.equilibrate(2, 0.005)
         v = s.observe(w["A"])
     assert np.isfinite(v)
+
+
+@pytest.mark.parametrize("name", ["h1_n12", "h3_n8"])
+def test_hermite_third_order_response_matches_the_oracle(pk, name):
+    """R^(3) of Eq. (3Dresponse) at one waiting time in the Hermite basis."""
+    w = SMALL[name]
+    M = w["M"]
+    A = optical(M)
+    B = wl.optical(M, lin=[0.5, 0.8, -0.3][:M], quad=[[0.1, 0.0, 0.05], [0.0, 0.2, 0.0], [0.05, 0.0, -0.1]][:M])
+    B["quad"] = [r[:M] for r in B["quad"]]
+    say(f"[hermite response_3d] {name}")
+    T = oh.tables(w)
+    Ceq = oh.equilibrate(w, 10, 0.004, T)
+    ref = oh.response_3d(w, A, B, B, A, Ceq, 4, 3, 5, 2, 2, 0.004, T)
+    with pk.Solver(pk.params_from_workload(w)) as s:
+        s.equilibrate(10, 0.004)
+        got = s.response_3d(A, B, B, A, 4, 3, 5, 2, 2, 0.004)
+    err = rel_l2(got, ref)
+    say(f"    R3 rel L2 {err:.2e}")
+    assert err < FP64_TOL
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_hermite_graph_and_eager_waves_agree(pk, monkeypatch, prec):
+    """Hermite-basis waves captured as HIP graphs and issued directly give
+    identical R, over three calls that replay the cached graph."""
+    w = SMALL["h3_c8"]
+    base = wl.workload("three_mode_24")
+    A, B = base["A"], base["B"]
+    code = pk.CHFPE_FP64 if prec == "f64" else pk.CHFPE_FP32
+    say(f"[hermite graph vs eager] {prec}")
+    monkeypatch.setenv("CHFPE_NO_GRAPH", "1")
+    with pk.Solver(pk.params_from_workload(w, precision=code, batch=3)) as s:
+        s.equilibrate(5, 0.004)
+        eager = s.response_2d(A, B, A, 7, 5, 1, 2, 0.004)
+    monkeypatch.setenv("CHFPE_NO_GRAPH", "0")
+    with pk.Solver(pk.params_from_workload(w, precision=code, batch=3)) as s:
+        s.equilibrate(5, 0.004)
+        for rep in range(3):
+            got = s.response_2d(A, B, A, 7, 5, 1, 2, 0.004)
+            assert np.array_equal(got, eager), rep
+            s.set_state(s.get_state())
+            s.observe(A)

@@ -188,3 +188,24 @@ def test_hermite_linear_response_approaches_the_grid_result():
     err = np.linalg.norm(Rh - Rg) / np.linalg.norm(Rg)
     print("R1 Hermite vs grid", err)
     assert err < 1e-3
+
+
+def test_hermite_third_order_response_approaches_the_grid_result():
+    """R^(3) at one waiting time: the grid oracle's result on p grids of 48
+    and 96 points (same q grid) converges to the Hermite oracle's at sixth
+    order (three excitations spread the state over many Hermite functions,
+    so the 48-point grid is still 6% off; the Hermite series with 10
+    functions is within 1.3e-6 of one with 24)."""
+    w = _w(1, 14, 10, 2)
+    A = wl.optical(1, lin=[1.0], quad=[[0.2]])
+    B = wl.optical(1, lin=[0.5], quad=[[0.1]])
+    dt = 0.01
+    Ch = oh.equilibrate(w, 100, dt)
+    Rh = oh.response_3d(w, A, B, B, A, Ch, 6, 10, 12, 2, 2, dt)
+    errs = []
+    for Np in (48, 96):
+        g = _grid_w(w, Np, 9.0)
+        Rg = orc.response_3d(g, A, B, B, A, orc.equilibrate(g, 100, dt), 6, 10, 12, 2, 2, dt)
+        errs.append(np.linalg.norm(Rg - Rh) / np.linalg.norm(Rh))
+    print("R3 grid vs Hermite", errs)
+    assert errs[0] / errs[1] > 30.0 and errs[1] < 2e-3
