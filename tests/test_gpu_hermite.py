@@ -204,3 +204,23 @@ def test_hermite_graph_and_eager_waves_agree(pk, monkeypatch, prec):
             assert np.array_equal(got, eager), rep
             s.set_state(s.get_state())
             s.observe(A)
+
+
+def test_hermite_context_has_no_tiles_to_tune_and_no_closure(pk):
+    """chfpe_autotune returns at once on a Hermite context (one k_hcube shape)
+    and leaves the results unchanged; the closure calls are refused (EINVAL),
+    as the closure is defined for the p grid."""
+    w = SMALL["h2_n10"]
+    C = hstate(w, seed=9)
+    with pk.Solver(pk.params_from_workload(w)) as s:
+        s.set_state(C)
+        s.rhs()
+        before = s.get_state()
+        cfg = s.autotune(2)
+        assert cfg["pcube"] == 0
+        s.set_state(C)
+        s.rhs()
+        assert np.array_equal(s.get_state(), before)
+        for call in (lambda: s.set_closure(np.zeros(4)), lambda: s.closure_moments()):
+            with pytest.raises(pk.ChfpeError):
+                call()
