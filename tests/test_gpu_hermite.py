@@ -51,6 +51,11 @@ SMALL = {
     "h3_c8": hw("three_mode_24", [8, 8, 8], [4, 4, 4], 2),
     "h3_c12": hw("three_mode_24", [12, 12, 12], [3, 3, 3], 2),
     "h3_c24": hw("three_mode_24", [24, 24, 24], [3, 2, 3], 1),
+    # edge shapes: a 48-point q_1 line (the largest bucket), depth 0 (no
+    # hierarchy neighbours), the minimum of two Hermite functions
+    "h1_n48": hw("one_mode_48", [48], [4], 2),
+    "h2_k0": hw("two_mode_32", [7, 11], [2, 3], 0),
+    "h3_nh2": hw("three_mode_24", [6, 9, 5], [2, 2, 2], 2),
 }
 
 
