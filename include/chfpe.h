@@ -319,7 +319,12 @@ int chfpe_autotune(chfpe_ctx *ctx, int32_t n_steps);
  * the whole p block (k_pcube; out[0], out[9] then describe no launch), out[12]
  * 1 when that kernel is the streamed form k_pcube_s (the default for p_1
  * axes up to 16 points; CHFPE_TUNE_PC_STREAM=0/1 forces either form).
- * Writes min(n, 13) values and returns that count. */
+ * Hermite basis: out[13] the k_hcube tasks per XCD chunk (the XCDs take
+ * chunks of consecutive tasks in turn; 0: one contiguous range each) and
+ * out[14] the width of the k_2 tiles of its task order (three modes; 1
+ * otherwise), set by CHFPE_TUNE_HC_CHUNK and CHFPE_TUNE_HC_KTILE; 0 for the
+ * grid basis.  The task order does not change any result.
+ * Writes min(n, 15) values and returns that count. */
 int chfpe_tile_config(const chfpe_ctx *ctx, int32_t *out, int32_t n);
 
 /* ---- Learned per-axis closure (coarse grids) -------------------------------

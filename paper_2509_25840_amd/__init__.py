@@ -497,14 +497,14 @@ class Solver:
 
     def tile_config(self) -> dict:
         """chfpe_tile_config as a dict."""
-        out = (ctypes.c_int32 * 13)()
-        k = lib().chfpe_tile_config(self._ctx, out, 13)
+        out = (ctypes.c_int32 * 15)()
+        k = lib().chfpe_tile_config(self._ctx, out, 15)
         if k < 0:
             self._check(k)
         keys = ("pblock_blocks_per_task", "pblock_split_lines", "pblock_threads", "qpass_positions",
                 "qpass_acc_positions", "qpass_threads", "request_pblock_blocks",
                 "request_split", "request_qpass_positions", "pblock_run", "request_pblock_run", "pcube",
-                "pcube_stream")
+                "pcube_stream", "hcube_chunk", "hcube_ktile")
         return {keys[i]: int(out[i]) for i in range(k)}
 
     def kernel_times(self) -> dict:

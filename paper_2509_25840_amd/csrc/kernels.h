@@ -399,6 +399,16 @@ __device__ __forceinline__ int xcd_task(const int bid, const int nblk) {
   return (bid & 7) * per + (bid >> 3);
 }
 
+// Chunked form: workgroups go to the XCDs in turn (bid & 7), and each XCD
+// takes every eighth chunk of G consecutive tasks, so the eight XCDs walk
+// one task order side by side (the shared last-level cache then sees one
+// front) while neighbouring tasks of a chunk share an L2.  Needs nblk to
+// be a multiple of 8 G.
+__device__ __forceinline__ int xcd_chunk_task(const int bid, const int G) {
+  const int j = bid >> 3;
+  return (((j / G) << 3) + (bid & 7)) * G + j % G;
+}
+
 // ---------------------------------------------------------------------------
 // Tile descriptions passed by value.
 // ---------------------------------------------------------------------------
@@ -693,6 +703,8 @@ struct PCube {
   int plane;       // N2 * N3: threads that own a p_1 line
   int rs;          // LDS row stride of a plane field: N3 plus a pad
   int ntasks, nblk;
+  int chunk;       // k_hcube: tasks per XCD chunk (0: one contiguous range per XCD)
+  int ktile;       // k_hcube, three modes: width of the k_2 tiles of the task order
 };
 
 // Largest workgroup of k_pcube for a p_1 bucket: acc and g1 take
@@ -1521,6 +1533,25 @@ constexpr int kHcV2 = 20, kHcV3 = kHcV2 + kTab;
 constexpr int kHCubeCF = kHcV3 + kTab;
 constexpr int kHCubePL = 2;  // q_1 planes per round
 
+// Task order of k_hcube: branch slowest, then the Hermite multi-index kb,
+// the element fastest.  For three modes kb walks k_2 in tiles of width T
+// (k_3 fastest, then k_2 within the tile, then k_1), so the k_1 neighbours
+// of a task are N_3 T multi-indices away rather than N_2 N_3; kb -> kl (the
+// storage index, k_3 fastest) is a bijection for any 1 <= T.
+__device__ __forceinline__ int hcube_kl(const Geom &g, const int T, const int kb) {
+  if (g.M < 3 || T >= g.Np[1]) return kb;
+  const int N1 = g.Np[0], N2 = g.Np[1], N3 = g.Np[2];
+  const int per_tile = N1 * T * N3;
+  const int tt = kb / per_tile;
+  const int w = min(T, N2 - tt * T);  // the last tile may be narrower
+  int r = kb - tt * per_tile;
+  const int k3 = r % N3;
+  r /= N3;
+  const int k1 = r / w;
+  const int k2 = tt * T + (r - k1 * w);
+  return (k1 * N2 + k2) * N3 + k3;
+}
+
 template <typename T, int NB1, bool SPLIT, int EPI>
 __global__ void __launch_bounds__((hcube_max_threads<T, NB1>()))
 k_hcube(const Geom g, const Tabs tb, const PCube pc, const T *__restrict__ X, const T *__restrict__ y,
@@ -1530,7 +1561,7 @@ k_hcube(const Geom g, const Tabs tb, const PCube pc, const T *__restrict__ X, co
   constexpr int RC = 2;  // stencil reach along q_1
   constexpr T third = T(1.0 / 3.0);
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int task = xcd_task(blockIdx.x, pc.nblk);
+  const int task = pc.chunk > 0 ? xcd_chunk_task(blockIdx.x, pc.chunk) : xcd_task(blockIdx.x, pc.nblk);
   if (task >= pc.ntasks) return;
   const int N1 = SPLIT ? NB1 : pc.N1, N2 = SPLIT ? NB1 : pc.N2, N3 = SPLIT ? NB1 : pc.N3;
   const int plane = SPLIT ? NB1 * NB1 : pc.plane;
@@ -1538,11 +1569,12 @@ k_hcube(const Geom g, const Tabs tb, const PCube pc, const T *__restrict__ X, co
   T *CF = reinterpret_cast<T *>(smem_raw);
   T *G2 = CF + kHCubeCF;  // [PL][N2][rs]
   T *G3 = G2 + PL * N2 * rs;
-  const int ne_all = g.ne * g.nbatch;
-  const int ea = task % ne_all;  // (branch, element) fastest: the elements of one k are adjacent tasks
-  const int kl = task / ne_all;  // Hermite multi-index, k_M fastest
-  const int br = ea / g.ne;
-  const int e = ea - br * g.ne;
+  const int per_br = g.ne * g.P;
+  const int br = task / per_br;
+  const int kb = (task - br * per_br) / g.ne;
+  const int e = task - br * per_br - kb * g.ne;  // the elements of one k are adjacent tasks
+  const int ea = br * g.ne + e;
+  const int kl = hcube_kl(g, pc.ktile, kb);  // Hermite multi-index, k_M fastest in storage
   const int tid = threadIdx.x;
   const bool own = tid < plane;
   const int j2 = own ? tid / N3 : 0;

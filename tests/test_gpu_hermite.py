@@ -229,3 +229,40 @@ def test_hermite_context_has_no_tiles_to_tune_and_no_closure(pk):
         for call in (lambda: s.set_closure(np.zeros(4)), lambda: s.closure_moments()):
             with pytest.raises(pk.ChfpeError):
                 call()
+
+
+@pytest.mark.parametrize("name", ["h3_n8", "h3_c12", "h2_n10"])
+def test_hermite_task_order_does_not_change_results(pk, monkeypatch, name):
+    """k_hcube's task order (XCD chunks, k_2 tiles) only schedules the tasks:
+    RK4 steps and a batched 2D response are bitwise equal under the default
+    order, one contiguous range per XCD, and chunks of 3 with k_2 tiles of 2
+    (ragged last tiles)."""
+    w = SMALL[name]
+    M = w["M"]
+    base = wl.workload({2: "two_mode_32", 3: "three_mode_24"}[M])
+    A, B = base["A"], base["B"]
+    C = hstate(w, seed=11)
+    ne = oh.shape(w)[0]
+    res = {}
+    for chunk, ktile in ((None, None), ("0", "0"), ("3", "2")):
+        for var, val in (("CHFPE_TUNE_HC_CHUNK", chunk), ("CHFPE_TUNE_HC_KTILE", ktile)):
+            if val is None:
+                monkeypatch.delenv(var, raising=False)
+            else:
+                monkeypatch.setenv(var, val)
+        say(f"[hermite task order] {name} chunk={chunk} ktile={ktile}")
+        with pk.Solver(pk.params_from_workload(w)) as s:
+            cfg = s.tile_config()
+            want_chunk = 4 * ne if chunk is None else int(chunk)
+            want_tile = (min(3, w["Np"][1]) if ktile in (None, "0") else min(int(ktile), w["Np"][1])) if M == 3 else 1
+            assert (cfg["hcube_chunk"], cfg["hcube_ktile"]) == (want_chunk, want_tile), cfg
+            s.set_state(C)
+            s.propagate(2, 0.003)
+            st = s.get_state()
+        with pk.Solver(pk.params_from_workload(w, batch=3)) as s:
+            s.equilibrate(4, 0.004)
+            r2 = s.response_2d(A, B, A, 4, 3, 1, 2, 0.004)
+        res[(chunk, ktile)] = (st, r2)
+    ref = res[(None, None)]
+    for key, (st, r2) in res.items():
+        assert np.array_equal(st, ref[0]) and np.array_equal(r2, ref[1]), key
