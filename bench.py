@@ -898,9 +898,27 @@ def main(argv=None):
             ev[i + 1].record()
         torch.cuda.synchronize()
         copy_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(3)]
+        # the read/write mixes of the stage passes with nothing else to do,
+        # over 4 GiB arrays: writes only, one, two and three reads per write
+        # (best of three each)
+        mbytes = 4 << 30
+        srcs = [torch.zeros(mbytes // 8, dtype=torch.float64, device="cuda") for _ in range(4)]
+        mix_GBps = {"bytes_per_array": mbytes}
+        for ns in (0, 1, 2, 3):
+            best = float("inf")
+            for _ in range(3):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                pk.stream_mix(srcs[3], srcs[:ns], mbytes)
+                e1.record()
+                torch.cuda.synchronize()
+                best = min(best, e0.elapsed_time(e1))
+            mix_GBps[f"{ns}r1w"] = (ns + 1) * mbytes / (best * 1e-3) / 1e9
+        del srcs
         print(json.dumps({"mode": "kernels", "workload": args.workload, "rk4_steps": args.rk4_steps,
                           "values_per_state": S, "copy_bytes": nbytes, "copies": 3,
                           "copy_ms": copy_ms, "copy_GBps": 2 * nbytes / (min(copy_ms) * 1e-3) / 1e9,
+                          "stream_mix_GBps": mix_GBps,
                           "kernel_bytes": {k: v[2] for k, v in kt.items() if v[0] > 0},
                           "kernel_ms": {k: v[1] for k, v in kt.items() if v[0] > 0}}), flush=True)
         solver.close()

@@ -270,8 +270,19 @@ int chfpe_spectrum_2d_noalloc(const double *R, int64_t n_t1, int64_t n_t2, doubl
                               double *I, void *hip_stream);
 
 /* Bandwidth reference: copy `bytes` bytes (a multiple of 16) from src to
- * dst, both device pointers, with a plain streaming kernel on hip_stream. */
+ * dst, both device pointers, with a plain streaming kernel on hip_stream
+ * (eight 16-byte loads in flight per thread, up to 64 workgroups per CU).
+ * EINVAL for NULL pointers or a size that is not a multiple of 16. */
 int chfpe_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
+
+/* Bandwidth reference for other read/write mixes: dst[i] = a[i] + b[i] +
+ * c[i] over the first nsrc of the sources (nsrc = 0..3; 0 writes zeros),
+ * all device arrays of `bytes` bytes read as FP64 (a multiple of 16).  The
+ * stage passes read two or three state arrays per one written; this kernel
+ * moves the same mix with nothing else to do.  Sources past nsrc may be NULL.
+ * EINVAL for nsrc out of range, a missing pointer or a bad size. */
+int chfpe_stream_mix(void *dst, const void *a, const void *b, const void *c, int32_t nsrc, size_t bytes,
+                     void *hip_stream);
 
 /* Per-kernel timing with HIP events on the context's stream: every
  * `every`-th RK4 step (0 turns timing off) each launch of that step is

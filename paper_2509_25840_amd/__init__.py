@@ -15,7 +15,7 @@ import os
 import numpy as np
 
 __all__ = ["Params", "Optical", "Solver", "ChfpeError", "lib", "params_from_workload",
-           "optical_from_dict", "workspace_bytes", "stream_copy", "spectrum_1d", "spectrum_2d", "spectrum_2dir",
+           "optical_from_dict", "workspace_bytes", "stream_copy", "stream_mix", "spectrum_1d", "spectrum_2d", "spectrum_2dir",
            "closure_rows", "closure_features", "closure_eval", "closure_grad", "ClosureTrainer",
            "CLOSURE_PARAMS", "LIB_PATH"]
 
@@ -111,6 +111,8 @@ def lib():
     L.chfpe_spectrum_2dir.restype = ctypes.c_int
     L.chfpe_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
     L.chfpe_stream_copy.restype = ctypes.c_int
+    L.chfpe_stream_mix.argtypes = [vp, vp, vp, vp, i32, ctypes.c_size_t, vp]
+    L.chfpe_stream_mix.restype = ctypes.c_int
     L.chfpe_set_kernel_timing.argtypes = [vp, i32]
     L.chfpe_set_kernel_timing.restype = ctypes.c_int
     L.chfpe_kernel_times.argtypes = [vp, i32, ctypes.POINTER(i64), dp, dp, ctypes.POINTER(ctypes.c_char_p)]
@@ -193,6 +195,18 @@ def stream_copy(dst, src, nbytes: int, stream=None) -> None:
                                  ctypes.c_size_t(nbytes), ctypes.c_void_p(s.cuda_stream))
     if rc != 0:
         raise ChfpeError(rc, "stream copy failed")
+
+
+def stream_mix(dst, srcs, nbytes: int, stream=None) -> None:
+    """Bandwidth reference for read/write mixes: dst = sum of the tensors in
+    srcs (0 to 3 of them; FP64 pairs), over nbytes bytes."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    ptr = [ctypes.c_void_p(t.data_ptr()) for t in srcs] + [ctypes.c_void_p(None)] * (3 - len(srcs))
+    rc = lib().chfpe_stream_mix(ctypes.c_void_p(dst.data_ptr()), ptr[0], ptr[1], ptr[2], len(srcs),
+                                ctypes.c_size_t(nbytes), ctypes.c_void_p(s.cuda_stream))
+    if rc != 0:
+        raise ChfpeError(rc, "stream mix failed")
 
 
 def _fptr(a: np.ndarray):

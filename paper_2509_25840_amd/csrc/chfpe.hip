@@ -1956,12 +1956,38 @@ int chfpe_use_state_as_equilibrium(chfpe_ctx *c) {
   return CHFPE_OK;
 }
 
+// 64 workgroups of 256 threads per CU (256 CUs), fewer for small copies
+static int stream_grid(long long n16) {
+  return (int)std::max(1LL, std::min(16384LL, (n16 + 256LL * kStreamU - 1) / (256LL * kStreamU)));
+}
+
 int chfpe_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream) {
   if (!dst || !src || (bytes % 16) != 0) return CHFPE_EINVAL;
   const long long n16 = (long long)(bytes / 16);
-  // 8 workgroups of 256 threads per CU (256 CUs)
-  hipLaunchKernelGGL(k_stream_copy, dim3(2048), dim3(256), 0, reinterpret_cast<hipStream_t>(hip_stream),
+  if (n16 == 0) return CHFPE_OK;
+  hipLaunchKernelGGL(k_stream_copy, dim3(stream_grid(n16)), dim3(256), 0, reinterpret_cast<hipStream_t>(hip_stream),
                      reinterpret_cast<uint4 *>(dst), reinterpret_cast<const uint4 *>(src), n16);
+  return hipGetLastError() == hipSuccess ? CHFPE_OK : CHFPE_EDEVICE;
+}
+
+int chfpe_stream_mix(void *dst, const void *a, const void *b, const void *c, int32_t nsrc, size_t bytes,
+                     void *hip_stream) {
+  if (!dst || nsrc < 0 || nsrc > 3 || (bytes % 16) != 0) return CHFPE_EINVAL;
+  if ((nsrc >= 1 && !a) || (nsrc >= 2 && !b) || (nsrc >= 3 && !c)) return CHFPE_EINVAL;
+  const long long n16 = (long long)(bytes / 16);
+  if (n16 == 0) return CHFPE_OK;
+  auto *d = reinterpret_cast<double2 *>(dst);
+  auto *pa = reinterpret_cast<const double2 *>(a);
+  auto *pb = reinterpret_cast<const double2 *>(b);
+  auto *pc = reinterpret_cast<const double2 *>(c);
+  const dim3 grid(stream_grid(n16));
+  const hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  switch (nsrc) {
+    case 0: hipLaunchKernelGGL(k_stream_mix<0>, grid, dim3(256), 0, st, d, pa, pb, pc, n16); break;
+    case 1: hipLaunchKernelGGL(k_stream_mix<1>, grid, dim3(256), 0, st, d, pa, pb, pc, n16); break;
+    case 2: hipLaunchKernelGGL(k_stream_mix<2>, grid, dim3(256), 0, st, d, pa, pb, pc, n16); break;
+    default: hipLaunchKernelGGL(k_stream_mix<3>, grid, dim3(256), 0, st, d, pa, pb, pc, n16); break;
+  }
   return hipGetLastError() == hipSuccess ? CHFPE_OK : CHFPE_EDEVICE;
 }
 

@@ -1475,21 +1475,54 @@ k_scatter_r(const double *__restrict__ Rw, double *__restrict__ R, const int n_t
   R[(long long)j2 * n_t1 + j0 + b] = Rw[(long long)j2 * B + b];
 }
 
-// dst = src, 16-byte vectors: each thread keeps four loads in flight before
-// it stores (a grid-stride loop over a few workgroups per CU), the form that
-// reaches the device's streaming bandwidth
+// Bandwidth references.  k_stream_copy: dst = src in 16-byte vectors;
+// k_stream_mix<NS>: dst = the sum of NS sources (pairs of doubles; NS = 0
+// writes zeros), the read/write mixes of the streaming passes.  Each thread
+// keeps eight vectors per source in flight before it stores, in a
+// grid-stride loop over many workgroups per CU.
+constexpr int kStreamU = 8;
 __global__ void __launch_bounds__(256)
 k_stream_copy(uint4 *__restrict__ dst, const uint4 *__restrict__ src, const long long n16) {
   const long long st = (long long)gridDim.x * 256;
   long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-  for (; i + 3 * st < n16; i += 4 * st) {
-    const uint4 a = src[i], b = src[i + st], c = src[i + 2 * st], d = src[i + 3 * st];
-    dst[i] = a;
-    dst[i + st] = b;
-    dst[i + 2 * st] = c;
-    dst[i + 3 * st] = d;
+  for (; i + (kStreamU - 1) * st < n16; i += kStreamU * st) {
+    uint4 v[kStreamU];
+#pragma unroll
+    for (int u = 0; u < kStreamU; ++u) v[u] = src[i + u * st];
+#pragma unroll
+    for (int u = 0; u < kStreamU; ++u) dst[i + u * st] = v[u];
   }
   for (; i < n16; i += st) dst[i] = src[i];
+}
+
+template <int NS>
+__global__ void __launch_bounds__(256)
+k_stream_mix(double2 *__restrict__ dst, const double2 *__restrict__ a, const double2 *__restrict__ b,
+             const double2 *__restrict__ c, const long long n16) {
+  const long long st = (long long)gridDim.x * 256;
+  long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  auto sum = [&](const long long j) {
+    double2 v = NS >= 1 ? a[j] : double2{0.0, 0.0};
+    if (NS >= 2) {
+      const double2 w = b[j];
+      v.x += w.x;
+      v.y += w.y;
+    }
+    if (NS >= 3) {
+      const double2 w = c[j];
+      v.x += w.x;
+      v.y += w.y;
+    }
+    return v;
+  };
+  for (; i + (kStreamU - 1) * st < n16; i += kStreamU * st) {
+    double2 v[kStreamU];
+#pragma unroll
+    for (int u = 0; u < kStreamU; ++u) v[u] = sum(i + u * st);
+#pragma unroll
+    for (int u = 0; u < kStreamU; ++u) dst[i + u * st] = v[u];
+  }
+  for (; i < n16; i += st) dst[i] = sum(i);
 }
 
 

@@ -103,6 +103,20 @@ def test_null_context_calls_are_rejected(binding):
     L.chfpe_destroy(None)
 
 
+def test_stream_references_reject_bad_arguments(binding):
+    # the checks come before any launch: the pointers are never dereferenced
+    L = binding.lib()
+    fake = ctypes.c_void_p(1 << 20)
+    assert L.chfpe_stream_copy(fake, fake, 24, None) == binding.CHFPE_EINVAL  # not a multiple of 16
+    assert L.chfpe_stream_copy(None, fake, 32, None) == binding.CHFPE_EINVAL
+    assert L.chfpe_stream_mix(fake, fake, None, None, 2, 64, None) == binding.CHFPE_EINVAL  # b missing
+    assert L.chfpe_stream_mix(fake, None, None, None, 4, 64, None) == binding.CHFPE_EINVAL
+    assert L.chfpe_stream_mix(fake, None, None, None, -1, 64, None) == binding.CHFPE_EINVAL
+    assert L.chfpe_stream_mix(None, None, None, None, 0, 64, None) == binding.CHFPE_EINVAL
+    assert L.chfpe_stream_mix(fake, fake, fake, fake, 3, 40, None) == binding.CHFPE_EINVAL
+    assert L.chfpe_stream_mix(fake, None, None, None, 0, 0, None) == binding.CHFPE_OK  # nothing to do
+
+
 def test_p_block_tiling_limit_is_enforced(binding):
     # the last two p axes are one LDS tile of k_pblock: N_{M-1} needs a
     # divisor d with d * N_M <= 256 and N_{M-1} <= 4 d; shapes it cannot
