@@ -68,6 +68,29 @@ def source_hash(read=None) -> str:
     return h.hexdigest()[:16]
 
 
+def stream_references(pk) -> dict:
+    """HBM rates of plain streaming kernels with the read/write mixes of the
+    stage passes, over 4 GiB arrays: writes only, one, two and three reads
+    per write (best of three each; chfpe_stream_mix on torch's stream)."""
+    import torch
+    mbytes = 4 << 30
+    srcs = [torch.zeros(mbytes // 8, dtype=torch.float64, device="cuda") for _ in range(4)]
+    out = {"bytes_per_array": mbytes}
+    for ns in (0, 1, 2, 3):
+        best = float("inf")
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            pk.stream_mix(srcs[3], srcs[:ns], mbytes)
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        out[f"{ns}r1w"] = (ns + 1) * mbytes / (best * 1e-3) / 1e9
+    del srcs
+    torch.cuda.empty_cache()
+    return out
+
+
 def rk4_steps(w) -> int:
     return (int(w["eq_steps"]) + (int(w["n_t1"]) - 1) * int(w["stride1"])
             + int(w["n_t1"]) * (int(w["n_t2"]) - 1) * int(w["stride2"]))
@@ -898,23 +921,7 @@ def main(argv=None):
             ev[i + 1].record()
         torch.cuda.synchronize()
         copy_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(3)]
-        # the read/write mixes of the stage passes with nothing else to do,
-        # over 4 GiB arrays: writes only, one, two and three reads per write
-        # (best of three each)
-        mbytes = 4 << 30
-        srcs = [torch.zeros(mbytes // 8, dtype=torch.float64, device="cuda") for _ in range(4)]
-        mix_GBps = {"bytes_per_array": mbytes}
-        for ns in (0, 1, 2, 3):
-            best = float("inf")
-            for _ in range(3):
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record()
-                pk.stream_mix(srcs[3], srcs[:ns], mbytes)
-                e1.record()
-                torch.cuda.synchronize()
-                best = min(best, e0.elapsed_time(e1))
-            mix_GBps[f"{ns}r1w"] = (ns + 1) * mbytes / (best * 1e-3) / 1e9
-        del srcs
+        mix_GBps = stream_references(pk)
         print(json.dumps({"mode": "kernels", "workload": args.workload, "rk4_steps": args.rk4_steps,
                           "values_per_state": S, "copy_bytes": nbytes, "copies": 3,
                           "copy_ms": copy_ms, "copy_GBps": 2 * nbytes / (min(copy_ms) * 1e-3) / 1e9,
@@ -1000,6 +1007,9 @@ def main(argv=None):
         cpu, parity, parity_of = cpu_baseline(w, solver, args.cpu_seconds, args.workload)
         cpu["sample"] += f"; the GPU result of the same work: relative L2 {parity:.1e} ({parity_of})"
     solver.close()
+    # context for the roofline (after the timed region): what plain streams
+    # with the passes' read/write mixes reach on this GPU
+    streams = stream_references(pk)
 
     out = {
         "metric": METRIC,
@@ -1023,6 +1033,7 @@ def main(argv=None):
                    "tiles": tiles, "tiles_arg": tiles_arg},
         "roofline": roofline,
         "path_roofline_16pass": step_alg,
+        "stream_reference_GBps": streams,
         "cpu_baseline": cpu,
         "spectrum_time_s": rk4_steps(w) * (ms_per_step / 1000.0) / steps_per,
         "parity_rel_l2_vs_oracle": parity,
