@@ -596,8 +596,9 @@ def main(argv=None):
         return 0
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the build targets a "
-              f"single MI355X; sharding over t1 branches is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the solver targets a "
+              f"single MI355X; splitting the t1 branches over GPUs (chfpe_response_2d_range per "
+              f"GPU) is not built", file=sys.stderr)
         return 2
 
     if args.tiles:
