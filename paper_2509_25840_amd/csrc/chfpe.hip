@@ -678,7 +678,7 @@ size_t pcube_lds_bytes(const Derived &d, size_t tsize, int pad, bool stream) {
   if (stream)
     return (kPCubeCF + 2 * (size_t)pcube_s_planes(nb1) * rows +
             (size_t)pcube_s_dlds((int)tsize, nb1) * d.Np[1] * pcube_n3(d)) * tsize;
-  return ((size_t)d.P + 2 * (size_t)pcube_planes(nb1) * rows) * tsize;
+  return ((size_t)d.P + 2 * (size_t)pcube_planes(nb1) * rows + (size_t)d.Np[0]) * tsize;  // + the p_1 table
 }
 
 // Three modes take k_pcube wherever its block fits (CHFPE_PCUBE=0 keeps the

@@ -35,6 +35,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 namespace chfpe {
 
@@ -730,7 +731,13 @@ k_pcube(const Geom g, const Tabs tb, const PCube pc, const T *__restrict__ X, TO
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int task = xcd_task(blockIdx.x, pc.nblk);
   if (task >= pc.ntasks) return;
-  const int N1 = pc.N1, N2 = pc.N2, N3 = pc.N3, plane = pc.plane;
+  // Cubic blocks solved by lane pairs (N1 = N2 = N3 = NB1): the neighbour
+  // loads run unconditionally (an absent neighbour points at h_n itself and
+  // enters with zero factors).  A load under a branch is waited for at the
+  // branch's join, which would serialise the planes' loads.
+  constexpr bool FULL = SPLIT;
+  const int N1 = pc.N1, N2 = pc.N2, N3 = pc.N3;
+  const int plane = pc.plane;
   const int rs = pc.rs;                       // LDS row stride (p_3 row plus a pad)
   T *H = reinterpret_cast<T *>(smem_raw);     // [N1][plane] copy of h_n
   T *G2 = H + N1 * plane;                     // [PL][N2][rs]
@@ -785,115 +792,227 @@ k_pcube(const Geom g, const Tabs tb, const PCube pc, const T *__restrict__ X, TO
 
   // ---- phase A: h_n and its p_1 neighbours over every plane
   T acc[NB1], g1[NB1];
+  // pointwise terms of h_n that involve p_1:
+  // n_1 zeta_1 gamma_1 V_1' p_1/2 h_{n-e_1} - V_1' beta p_1/(2 m_1) h_{n+e_1} - sum n gamma h_n
+  // (for PERTURB: -sum_s dX/dq_s beta p_s / 2 m_s h_n)
+  auto point_a = [&](const T h, const T hu, const T hd, const T p1) {
+    return PERTURB ? -(c23 + c1 * p1) * h : -dmp * h + p1 * (pwd[0] * hd - pwu[0] * hu);
+  };
+  auto plane_a = [&](const int i, const T h, const T hu, const T hd, const T p1) {
+    if (!FULL) acc[i] = point_a(h, hu, hd, p1);
+    g1[i] = PERTURB ? Fv[0] * h : Fv[0] * h + vu[0] * hu + vd[0] * hd;
+    if (own) H[i * plane + tid] = h;
+  };
+  // FULL: p_1 values from an LDS copy of their table (a vector load of a
+  // table value issued after the next group's loads would wait for all of
+  // them), and load groups of GA planes whose offsets pass through an empty
+  // asm statement: that keeps each group's loads after the previous
+  // group's LDS stores (loads of read-only memory could otherwise all be
+  // hoisted to the top, which exhausts the registers)
+  T *P1t = G3 + PL * N2 * rs;
+  constexpr int GA = 4;
+  // RU, RD (std::bool_constant): read the p_1 neighbour above / below
+  auto load_g = [&](const int i0, T (&h)[GA], T (&u)[GA], T (&d)[GA], T (&pp)[GA], const bool with_h, auto RU,
+                    auto RD) {
+    uint32_t b = own_off;
+    asm volatile("" : "+v"(b));
 #pragma unroll
-  for (int i = 0; i < NB1; ++i) {
-    acc[i] = T(0);
-    g1[i] = T(0);
-    if (i < N1) {
-      const uint32_t o = (uint32_t)(i * plane) + own_off;
-      const T h = at_u32(Xe, o);
-      const T p1 = T(tb.pg[0 * kTab + i]);
-      if (PERTURB) {
-        acc[i] = -(c23 + c1 * p1) * h;
-        g1[i] = Fv[0] * h;
-      } else {
-        const T hu = hu_[0] ? at_u32(Xu[0], o) : T(0);
-        const T hd = hd_[0] ? at_u32(Xd[0], o) : T(0);
-        // n_1 zeta_1 gamma_1 V_1' p_1/2 h_{n-e_1} - V_1' beta p_1/(2 m_1) h_{n+e_1} - sum n gamma h_n
-        acc[i] = -dmp * h + p1 * (pwd[0] * hd - pwu[0] * hu);
-        g1[i] = Fv[0] * h + vu[0] * hu + vd[0] * hd;
+    for (int k = 0; k < GA; ++k) {
+      const uint32_t o = (uint32_t)((i0 + k) * plane) + b;
+      pp[k] = P1t[i0 + k];
+      h[k] = with_h ? at_u32(Xe, o) : H[(i0 + k) * plane + tid];
+      u[k] = (PERTURB || !decltype(RU)::value) ? T(0) : at_u32(Xu[0], o);
+      d[k] = (PERTURB || !decltype(RD)::value) ? T(0) : at_u32(Xd[0], o);
+    }
+  };
+  const std::true_type yes{};
+  const std::false_type no{};
+  if constexpr (FULL) {
+    // only the p_1 field is kept through phase A (the pointwise terms are
+    // added at the end, from the LDS copy of h_n and a second read of the
+    // p_1 neighbours), so two groups of loads fit in flight
+    if (tid < N1) P1t[tid] = T(tb.pg[0 * kTab + tid]);
+    __syncthreads();
+    // one loop per combination of p_1 neighbours the element has (one
+    // uniform branch around the loop), so that only those are read
+    auto sweep_a = [&](auto RU, auto RD) {
+      T ch[GA], cu[GA], cd[GA], cp[GA];
+      load_g(0, ch, cu, cd, cp, true, RU, RD);
+#pragma unroll
+      for (int i0 = 0; i0 < NB1; i0 += GA) {
+        T nh[GA], nu[GA], nd[GA], np[GA];
+        if (i0 + GA < NB1) load_g(i0 + GA, nh, nu, nd, np, true, RU, RD);
+#pragma unroll
+        for (int k = 0; k < GA; ++k) plane_a(i0 + k, ch[k], cu[k], cd[k], cp[k]);
+        if (i0 + GA < NB1) {
+#pragma unroll
+          for (int k = 0; k < GA; ++k) {
+            ch[k] = nh[k];
+            cu[k] = nu[k];
+            cd[k] = nd[k];
+            cp[k] = np[k];
+          }
+        }
       }
-      if (own) H[i * plane + tid] = h;
+    };
+    if (PERTURB || (!hu_[0] && !hd_[0]))
+      sweep_a(no, no);
+    else if (!hd_[0])
+      sweep_a(yes, no);
+    else if (!hu_[0])
+      sweep_a(no, yes);
+    else
+      sweep_a(yes, yes);
+  } else {
+#pragma unroll
+    for (int i = 0; i < NB1; ++i) {
+      acc[i] = T(0);
+      g1[i] = T(0);
+      if (i < N1) {
+        const uint32_t o = (uint32_t)(i * plane) + own_off;
+        const T h = at_u32(Xe, o);
+        const T hu = (!PERTURB && hu_[0]) ? at_u32(Xu[0], o) : T(0);
+        const T hd = (!PERTURB && hd_[0]) ? at_u32(Xd[0], o) : T(0);
+        plane_a(i, h, hu, hd, T(tb.pg[0 * kTab + i]));
+      }
     }
   }
   compact_inplace<T, NB1, CLOS>(g1, N1, T(g.dp_ca[0]), T(g.dp_cb[0]),
                                 CLOS ? tb.clos + g.M * 2 * kClosRows * kTab : nullptr);
 #pragma unroll
-  for (int i = 0; i < NB1; ++i) acc[i] += g1[i];
+  for (int i = 0; i < NB1; ++i) acc[i] = FULL ? g1[i] : acc[i] + g1[i];
 
   // ---- phase B: the p_2 and p_3 terms in rounds of PL planes
   const double *ct2 = CLOS ? tb.clos + (g.M + 1) * 2 * kClosRows * kTab : nullptr;
   const double *ct3 = CLOS ? tb.clos + (g.M + 2) * 2 * kClosRows * kTab : nullptr;
   // round loads: the p_2 and p_3 neighbours of PL planes (planes past the
   // block re-read its last plane: in bounds, unused)
-  auto load_round = [&](const int r, T (&u2)[PL], T (&d2)[PL], T (&u3)[PL], T (&d3)[PL]) {
+  // FULL: UP, D2, D3 (std::bool_constant) say which neighbours are read;
+  // the others are zero, as are their factors (a missing neighbour read
+  // anyway is the element itself, with zero factors).  Otherwise the
+  // element's own flags decide, at run time.
+  auto load_round = [&](const int r, T (&u2)[PL], T (&d2)[PL], T (&u3)[PL], T (&d3)[PL], auto UP, auto D2,
+                        auto D3) {
+    constexpr bool up = decltype(UP)::value, dn2 = decltype(D2)::value, dn3 = decltype(D3)::value;
+    uint32_t b = own_off;
+    if constexpr (FULL) asm volatile("" : "+v"(b));  // these loads stay in their round
 #pragma unroll
     for (int k = 0; k < PL; ++k) {
-      const uint32_t o = (uint32_t)(min(r * PL + k, N1 - 1) * plane) + own_off;
-      u2[k] = (!PERTURB && hu_[1]) ? at_u32(Xu[1], o) : T(0);
-      d2[k] = (!PERTURB && hd_[1]) ? at_u32(Xd[1], o) : T(0);
-      u3[k] = (!PERTURB && hu_[2]) ? at_u32(Xu[2], o) : T(0);
-      d3[k] = (!PERTURB && hd_[2]) ? at_u32(Xd[2], o) : T(0);
+      const uint32_t o = (uint32_t)(min(r * PL + k, N1 - 1) * plane) + b;
+      u2[k] = (!PERTURB && (FULL ? up : hu_[1])) ? at_u32(Xu[1], o) : T(0);
+      d2[k] = (!PERTURB && (FULL ? dn2 : hd_[1])) ? at_u32(Xd[1], o) : T(0);
+      u3[k] = (!PERTURB && (FULL ? up : hu_[2])) ? at_u32(Xu[2], o) : T(0);
+      d3[k] = (!PERTURB && (FULL ? dn3 : hd_[2])) ? at_u32(Xd[2], o) : T(0);
     }
   };
-  T cu2[PL], cd2[PL], cu3[PL], cd3[PL];
-  load_round(0, cu2, cd2, cu3, cd3);
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const int i0 = r * PL;
-    if (i0 >= N1) break;  // uniform
-    T xu2[PL], xd2[PL], xu3[PL], xd3[PL];  // next round, in flight during this one
-    if (r + 1 < NR) load_round(r + 1, xu2, xd2, xu3, xd3);
-#pragma unroll
-    for (int k = 0; k < PL; ++k) {
-      const int i = i0 + k;
-      if (i < N1 && own) {
-        const T h = H[i * plane + tid];
-        acc[i] += q2d * cd2[k] - q2u * cu2[k] + q3d * cd3[k] - q3u * cu3[k];
-        const int li = (k * N2 + j2) * rs + j3;
-        G2[li] = Fv[1] * h + vu[1] * cu2[k] + vd[1] * cd2[k];
-        G3[li] = Fv[2] * h + vu[2] * cu3[k] + vd[2] * cd3[k];
-      }
-    }
-    __syncthreads();
-    // p_2 lines of G2 (fixed k, j3) and p_3 lines of G3 (fixed k, j2)
-    const int npl = min(PL, N1 - i0);
-    const int nl2 = npl * N3, nl = nl2 + npl * N2;
-    if (SPLIT) {
-      for (int hl = tid; hl < 2 * nl; hl += blockDim.x) {
-        const int l = hl >> 1;
-        if (l < nl2) {
-          const int k = l / N3, c = l - k * N3;
-          compact_split_regs<T, NB1, CLOS>(G2, k * N2 * rs + c, rs, hl & 1, T(g.dp_ca[1]), T(g.dp_cb[1]), ct2);
-        } else {
-          const int l3 = l - nl2;
-          compact_split_regs<T, NB1, CLOS>(G3, l3 * rs, 1, hl & 1, T(g.dp_ca[2]), T(g.dp_cb[2]), ct3);
-        }
-      }
-    } else {
-      for (int l = tid; l < nl; l += blockDim.x) {
-        if (l < nl2) {
-          const int k = l / N3, c = l - k * N3;
-          compact_lds<T, CLOS>(G2, k * N2 * rs + c, rs, N2, T(g.dp_ca[1]), T(g.dp_cb[1]), ct2);
-        } else {
-          compact_lds<T, CLOS>(G3, (l - nl2) * rs, 1, N3, T(g.dp_ca[2]), T(g.dp_cb[2]), ct3);
-        }
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < PL; ++k) {
-      const int i = i0 + k;
-      if (i < N1 && own) {
-        const int li = (k * N2 + j2) * rs + j3;
-        acc[i] += G2[li] + G3[li];
-      }
-    }
-    __syncthreads();  // the next round overwrites the planes
-    if (r + 1 < NR) {
-#pragma unroll
+  auto phase_b = [&](auto UP, auto D2, auto D3) {
+    T cu2[PL], cd2[PL], cu3[PL], cd3[PL];
+    load_round(0, cu2, cd2, cu3, cd3, UP, D2, D3);
+  #pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int i0 = r * PL;
+      if (i0 >= N1) break;  // uniform
+      T xu2[PL], xd2[PL], xu3[PL], xd3[PL];  // next round, in flight during this one
+      if (r + 1 < NR) load_round(r + 1, xu2, xd2, xu3, xd3, UP, D2, D3);
+  #pragma unroll
       for (int k = 0; k < PL; ++k) {
-        cu2[k] = xu2[k];
-        cd2[k] = xd2[k];
-        cu3[k] = xu3[k];
-        cd3[k] = xd3[k];
+        const int i = i0 + k;
+        if (i < N1 && own) {
+          const T h = H[i * plane + tid];
+          acc[i] += q2d * cd2[k] - q2u * cu2[k] + q3d * cd3[k] - q3u * cu3[k];
+          const int li = (k * N2 + j2) * rs + j3;
+          G2[li] = Fv[1] * h + vu[1] * cu2[k] + vd[1] * cd2[k];
+          G3[li] = Fv[2] * h + vu[2] * cu3[k] + vd[2] * cd3[k];
+        }
+      }
+      __syncthreads();
+      // p_2 lines of G2 (fixed k, j3) and p_3 lines of G3 (fixed k, j2)
+      const int npl = min(PL, N1 - i0);
+      const int nl2 = npl * N3, nl = nl2 + npl * N2;
+      if (SPLIT) {
+        for (int hl = tid; hl < 2 * nl; hl += blockDim.x) {
+          const int l = hl >> 1;
+          if (l < nl2) {
+            const int k = l / N3, c = l - k * N3;
+            compact_split_regs<T, NB1, CLOS>(G2, k * N2 * rs + c, rs, hl & 1, T(g.dp_ca[1]), T(g.dp_cb[1]), ct2);
+          } else {
+            const int l3 = l - nl2;
+            compact_split_regs<T, NB1, CLOS>(G3, l3 * rs, 1, hl & 1, T(g.dp_ca[2]), T(g.dp_cb[2]), ct3);
+          }
+        }
+      } else {
+        for (int l = tid; l < nl; l += blockDim.x) {
+          if (l < nl2) {
+            const int k = l / N3, c = l - k * N3;
+            compact_lds<T, CLOS>(G2, k * N2 * rs + c, rs, N2, T(g.dp_ca[1]), T(g.dp_cb[1]), ct2);
+          } else {
+            compact_lds<T, CLOS>(G3, (l - nl2) * rs, 1, N3, T(g.dp_ca[2]), T(g.dp_cb[2]), ct3);
+          }
+        }
+      }
+      __syncthreads();
+  #pragma unroll
+      for (int k = 0; k < PL; ++k) {
+        const int i = i0 + k;
+        if (i < N1 && own) {
+          const int li = (k * N2 + j2) * rs + j3;
+          acc[i] += G2[li] + G3[li];
+        }
+      }
+      __syncthreads();  // the next round overwrites the planes
+      if (r + 1 < NR) {
+  #pragma unroll
+        for (int k = 0; k < PL; ++k) {
+          cu2[k] = xu2[k];
+          cd2[k] = xd2[k];
+          cu3[k] = xu3[k];
+          cd3[k] = xd3[k];
+        }
       }
     }
-  }
+  };
+  // FULL: every neighbour is read (copies of phase B per combination of
+  // neighbours, as phase A has, spill registers and were slower)
+  phase_b(yes, yes, yes);
   if (!own) return;
+  if constexpr (FULL) {
+    // the pointwise terms of phase A, then the stores, in load groups; the
+    // second read covers only the neighbours the element has (one uniform
+    // branch around the whole loop, none inside it)
+    auto finish = [&](auto RU, auto RD) {
+      T ch[GA], cu[GA], cd[GA], cp[GA];
+      load_g(0, ch, cu, cd, cp, false, RU, RD);
 #pragma unroll
-  for (int i = 0; i < NB1; ++i)
-    if (i < N1) at_u32(Oe, (uint32_t)(i * plane + tid)) = TO(acc[i]);
+      for (int i0 = 0; i0 < NB1; i0 += GA) {
+        T nh[GA], nu[GA], nd[GA], np[GA];
+        if (i0 + GA < NB1) load_g(i0 + GA, nh, nu, nd, np, false, RU, RD);
+#pragma unroll
+        for (int k = 0; k < GA; ++k)
+          at_u32(Oe, (uint32_t)((i0 + k) * plane + tid)) = TO(acc[i0 + k] + point_a(ch[k], cu[k], cd[k], cp[k]));
+        if (i0 + GA < NB1) {
+#pragma unroll
+          for (int k = 0; k < GA; ++k) {
+            ch[k] = nh[k];
+            cu[k] = nu[k];
+            cd[k] = nd[k];
+            cp[k] = np[k];
+          }
+        }
+      }
+    };
+    if (PERTURB || (!hu_[0] && !hd_[0]))
+      finish(no, no);
+    else if (!hd_[0])
+      finish(yes, no);
+    else if (!hu_[0])
+      finish(no, yes);
+    else
+      finish(yes, yes);
+  } else {
+#pragma unroll
+    for (int i = 0; i < NB1; ++i)
+      if (i < N1) at_u32(Oe, (uint32_t)(i * plane + tid)) = TO(acc[i]);
+  }
 }
 
 // ---------------------------------------------------------------------------
