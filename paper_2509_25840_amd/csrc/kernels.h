@@ -731,10 +731,13 @@ k_pcube(const Geom g, const Tabs tb, const PCube pc, const T *__restrict__ X, TO
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int task = xcd_task(blockIdx.x, pc.nblk);
   if (task >= pc.ntasks) return;
-  // Cubic blocks solved by lane pairs (N1 = N2 = N3 = NB1): the neighbour
-  // loads run unconditionally (an absent neighbour points at h_n itself and
-  // enters with zero factors).  A load under a branch is waited for at the
-  // branch's join, which would serialise the planes' loads.
+  // Cubic blocks solved by lane pairs (N1 = N2 = N3 = NB1) schedule their
+  // loads explicitly: no load sits under a branch inside a loop (a load
+  // under a branch is waited for at the branch's join, which serialised the
+  // planes' loads).  Phase A and the final stores have one loop per
+  // combination of p_1 neighbours the element has; phase B reads every
+  // p_2, p_3 neighbour slot (an absent neighbour points at h_n itself and
+  // enters with zero factors).
   constexpr bool FULL = SPLIT;
   const int N1 = pc.N1, N2 = pc.N2, N3 = pc.N3;
   const int plane = pc.plane;
