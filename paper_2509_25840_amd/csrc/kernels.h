@@ -1415,6 +1415,61 @@ k_qpass(const Geom g, const Tabs tb, const QPass qp, const T *__restrict__ X, TO
     kb = T(-tb.pm[s * kTab + (pix0 / g.PS[s]) % g.Np[s]]);
   }
   const T cs = T(cst);
+  if ((EPI == EPI_ACC || EPI == EPI_H1) && Na == NMAX) {
+    // Full lines (one uniform branch): the epilogue's loads go in groups of
+    // four points, issued one group ahead.  In the per-point form below each
+    // point's load sits under an "i < Na" branch and is waited for before
+    // the next point's load is issued.  Each group's offset passes through
+    // an empty asm statement, which keeps its loads after the previous
+    // group's stores.  (The stage-final passes that read y or xo as well run
+    // at the device's streaming rate either way; grouped, they measured 1%
+    // slower.)
+    constexpr int GE = 4;  // NMAX is a multiple of 4
+    T ct[GE], cy[GE];
+    auto load_e = [&](const int i0, T (&tv)[GE], T (&yv)[GE]) {
+      uint32_t b = (uint32_t)lrel;
+      asm volatile("" : "+v"(b));
+#pragma unroll
+      for (int k = 0; k < GE; ++k) {
+        const long long ui = ebase + (long long)(i0 + k) * qp.sa;
+        tv[k] = T(at_u32(Tacc + ui, b));
+        yv[k] = EPI == EPI_H2 ? T(at_u32(y + ui, b)) : EPI == EPI_H4 ? T(at_u32(xo + ui, b)) : T(0);
+      }
+    };
+    load_e(0, ct, cy);
+#pragma unroll
+    for (int i0 = 0; i0 < NMAX; i0 += GE) {
+      T nt[GE], ny[GE];
+      if (i0 + GE < NMAX) load_e(i0 + GE, nt, ny);
+#pragma unroll
+      for (int k = 0; k < GE; ++k) {
+        const int i = i0 + k;
+        T kv = ka * d[i];
+        if (TWO) kv += kb * lds[i * rs + jb * qp.pc + c];
+        const long long ui = ebase + (long long)i * qp.sa;
+        if (EPI == EPI_ACC) {
+          at_u32(Tacc + ui, lrel) = TO(ct[k] + kv);
+        } else {
+          kv += ct[k];
+          TO &xov = at_u32(xo + ui, lrel);
+          if (EPI == EPI_OUT)
+            xov = TO(kv);
+          else if (EPI == EPI_H1)
+            xov = TO(f[i] + cs * kv);
+          else  // EPI_H2 (y) and EPI_H4 (xo itself)
+            xov = TO(cy[k] + cs * kv);
+        }
+      }
+      if (i0 + GE < NMAX) {
+#pragma unroll
+        for (int k = 0; k < GE; ++k) {
+          ct[k] = nt[k];
+          cy[k] = ny[k];
+        }
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < NMAX; ++i) {
     if (i < Na) {
